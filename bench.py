@@ -1,0 +1,221 @@
+"""Benchmark of the Wilson-fermion hot path on one MI355X.
+
+Headline (`value`): FP64 apply_H throughput in algorithmic GB/s on the 32^3 x 64 lattice with
+smooth synthetic SU(3) links (width 0.3, seed 3000).  One step = one full-lattice application of
+H in even/odd form (the H_eo and H_oe hops, 18-real FP64 links), inputs resident in HBM.
+Algorithmic bytes per hop output site: 2 spinors + 8 links = 192 + 192 + 8 * 144 = 1536 B.
+
+After the timed region the second half of the metric is measured on the same GPU (events on
+the library's stream): CG to a true FP64 residual of 1e-10 in plain FP64 and in mixed precision
+(FP32 and FP16 Krylov bulk, 12-real links, FP64 reliable updates), with the error against the
+FP64 solution, hop throughput of the other storage formats, and the filtered force.  The oracle
+is timed on the host for `cpu_baseline`.
+
+Prints exactly one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "apply_H GB/s (% HBM roofline); CG-to-1e-10 time, FP64 vs mixed/multi-RHS"
+HBM_PEAK_GBS = 8000.0
+DIMS = (64, 32, 32, 32)          # (L_t, L_z, L_y, L_x)
+KAPPA = 0.1575
+BYTES_PER_SITE = {("f64", 18): 1536, ("f64", 12): 1152, ("f32", 18): 768, ("f32", 12): 576, ("f16", 12): 296}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="only the timed apply_H region")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
+              f"domain decomposition is a design, not a build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1805_03560_amd import synth, whmc
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    T, Z, Y, X = DIMS
+    V = T * Z * Y * X
+    Vh = V // 2
+
+    t0 = time.time()
+    U = synth.smooth_links(DIMS, 3000, width=0.3, threads=min(16, os.cpu_count() or 1))
+    log(f"[bench] generated 32^3x64 smooth links in {time.time() - t0:.1f}s")
+    ctx = whmc.Context(DIMS, device=0)
+    ctx.load_gauge(torch.from_numpy(U).to(dev), unitarity_tol=1e-11)
+    del U
+    stream = torch.cuda.current_stream(dev)
+    psi = ctx.pack_spinor(torch.from_numpy(synth.gaussian_spinor(V, 3001)).to(dev), -1)
+    out = ctx.full_spinor()
+    torch.cuda.synchronize()
+
+    # ------------------------------------------------------------ timed region: apply_H FP64
+    for _ in range(args.warmup):
+        ctx.apply_H(psi, -1, out=out)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        ctx.apply_H(psi, -1, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = ev0.elapsed_time(ev1)
+    ms_per_step = ms / args.steps
+    bytes_per_launch = 1536 * Vh
+    value = 2 * bytes_per_launch * args.steps / (ms * 1e-3) / 1e9
+    achieved = bytes_per_launch / (ms_per_step / 2 * 1e-3) / 1e9
+    log(f"[bench] apply_H FP64: {ms_per_step:.3f} ms/step, {value:.1f} GB/s (wall {wall:.3f}s)")
+
+    result = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "apply_H, even/odd FP64, 18-real links, 32^3x64 smooth SU(3) links "
+                               "(width 0.3, seed 3000), anti-periodic time; one step = H_eo + H_oe",
+                   "lattice_t_z_y_x": list(DIMS), "sites": V, "kappa": KAPPA},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(bytes_per_launch)},
+    }
+
+    if not args.no_extras:
+        result.update(extras(ctx, whmc, torch, np, stream, Vh))
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline()
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+def measured_traffic(bytes_per_launch):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this kernel, if its
+    recorded source digest still matches the stencil sources (else null)."""
+    path = os.path.join(ROOT, "profiles", "hop_f64_l18_32x64_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_digest") != source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("device.h", "stencil.h", "core.hip"):
+        h.update(open(os.path.join(ROOT, "paper_1805_03560_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def time_events(fn, stream, torch, reps=1):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def extras(ctx, whmc, torch, np, stream, Vh):
+    from paper_1805_03560_amd import synth
+    out = {}
+    # hop throughput of every storage format (one H_eo launch, algorithmic bytes of that format)
+    fmt = {}
+    x64 = ctx.pack_spinor(torch.from_numpy(synth.gaussian_spinor(Vh, 3002)).to(ctx.device), 0)
+    for (p, pn), links in [((whmc.F64, "f64"), 18), ((whmc.F64, "f64"), 12), ((whmc.F32, "f32"), 18),
+                           ((whmc.F32, "f32"), 12), ((whmc.F16, "f16"), 12)]:
+        xin = x64 if p == whmc.F64 else ctx.convert_spinor(x64, whmc.F64, p)
+        o = ctx.half_spinor(p)
+        ctx.apply_H(xin, 0, prec=p, links=links, out=o)
+        ms = time_events(lambda: ctx.apply_H(xin, 0, prec=p, links=links, out=o), stream, torch, reps=20)
+        gbs = BYTES_PER_SITE[(pn, links)] * Vh / (ms * 1e-3) / 1e9
+        fmt[f"{pn}_l{links}"] = {"us_per_hop": round(ms * 1e3, 1), "GBps": round(gbs, 1),
+                                 "frac_hbm": round(gbs / HBM_PEAK_GBS, 3)}
+        log(f"[bench] hop {pn}-{links}: {ms * 1e3:.1f} us, {gbs:.0f} GB/s")
+    out["hop_formats"] = fmt
+
+    # CG to 1e-10: FP64 vs mixed precision (32^3 x 64, kappa = 0.1575)
+    b = ctx.pack_spinor(torch.from_numpy(synth.gaussian_spinor(Vh, 3003)).to(ctx.device), 0)
+    cgr = {}
+    x64s, st = ctx.cg_solve(b, [KAPPA], whmc.cg_params(tol=1e-10))      # warm (workspace allocation)
+    ref = x64s.clone()
+    t = {}
+    for name, prm in [("fp64", whmc.cg_params(tol=1e-10)),
+                      ("mixed_f32_l12", whmc.cg_params(tol=1e-10, prec=whmc.F32, links=whmc.L12, delta=0.1)),
+                      ("mixed_f16_l12", whmc.cg_params(tol=1e-10, prec=whmc.F16, links=whmc.L12, delta=0.1))]:
+        ctx.cg_solve(b, [KAPPA], prm)      # warm-up of this path
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        x, st = ctx.cg_solve(b, [KAPPA], prm)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        err = float(torch.linalg.vector_norm(x - ref) / torch.linalg.vector_norm(ref))
+        s = st[0]
+        t[name] = ms
+        cgr[name] = {"ms": round(ms, 2), "iters": s["iters"], "reliable_updates": s["reliable_updates"],
+                     "true_residual": s["true_residual"], "rel_err_vs_fp64_solution": err}
+        log(f"[bench] CG {name}: {ms:.1f} ms, {s['iters']} iters, res {s['true_residual']:.2e}, err {err:.2e}")
+    for name in ("mixed_f32_l12", "mixed_f16_l12"):
+        cgr[name]["speedup_vs_fp64"] = round(t["fp64"] / t[name], 3)
+    out["cg_32x64_kappa0.1575"] = cgr
+
+    # kappa^4-filtered pseudo-fermion force (n_t = 15), FP64 solves to 1e-10
+    phi = b
+    ms = time_events(lambda: ctx.force(phi, 2, 15, 29, KAPPA, 5.6, solver=whmc.cg_params(tol=1e-10)), stream, torch)
+    out["force_kappa4_nt15_ms"] = round(ms, 1)
+    log(f"[bench] filtered force (kappa^4, n_t=15): {ms:.1f} ms")
+    return out
+
+
+def cpu_baseline():
+    """the FP64 numpy oracle's even/odd hop, timed on this host on a bounded sample: H_eo on the
+    16^3 x 32 lattice (the oracle's numpy kernels run on one thread)."""
+    import numpy as np
+
+    from oracle import dirac
+    from oracle.lattice import Lattice
+    from paper_1805_03560_amd import synth
+    dims = (32, 16, 16, 16)
+    lat = Lattice(dims)
+    U = synth.smooth_links(dims, 2000)
+    x = synth.gaussian_spinor(lat.Vh, 2001)
+    dirac.apply_Hblock(lat, U, x, 0)
+    reps, t = 0, 0.0
+    t0 = time.perf_counter()
+    while t < 10.0 and reps < 50:
+        dirac.apply_Hblock(lat, U, x, 0)
+        reps += 1
+        t = time.perf_counter() - t0
+    gbs = 1536 * lat.Vh * reps / t / 1e9
+    log(f"[bench] oracle H_eo 16^3x32: {t / reps:.2f} s/hop, {gbs:.3f} GB/s")
+    return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} oracle H_eo applications on 16^3x32 (Vh={lat.Vh}), {t / reps:.2f} s each; "
+                      f"host {platform.processor() or platform.machine()}, os.cpu_count()={os.cpu_count()}"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,232 @@
+/*
+ * whmc.h -- C ABI of the MI355X (gfx950) hot path of two-flavour Wilson-fermion HMC with
+ * hopping-parameter-expansion filtering, after M. Hasenbusch, arXiv:1805.03560.
+ *
+ * Conventions (the paper leaves them open):
+ *   - lattice dims are (L_t, L_z, L_y, L_x); direction mu is axis mu (mu = 0 is time).
+ *     lex = ((t L_z + z) L_y + y) L_x + x, parity = (t+z+y+x) mod 2, cb = lex / 2.
+ *     All extents must be even and >= 2 (even/odd ordering, Sec. 2.2).
+ *   - gauge field periodic; fermion hops across the time boundary carry -1 (Sec. 4).
+ *   - chiral Euclidean gamma basis: gamma_0 = [[0,1],[1,0]], gamma_k = [[0,-i s_k],[i s_k,0]]
+ *     (s_k Pauli matrices, k = 1,2,3 acting along axes 1,2,3), gamma_5 = g0 g1 g2 g3.
+ *   - H has no factor 1/2:  M = 1 - kappa H,  M_oo = 1 - kappa^2 H_oe H_eo on the odd sites.
+ *   - momenta and forces are antihermitian traceless 3x3 matrices stored as 8 real coordinates on
+ *     T_a = i lambda_a / 2 (Gell-Mann lambda_a), so (Pi,Pi) = -2 sum Tr Pi^2 = sum pi_a^2.
+ *
+ * Memory.  Every field pointer is DEVICE memory owned by the caller (e.g. a torch tensor on the
+ * context's GPU); the library never frees it.  Device layouts ("whmc layout"):
+ *   half spinor F64   double2 [12][Vh]        complex component c = 3*spin+colour of site cb
+ *   half spinor F32   float4  [6][Vh]         complex components (2k, 2k+1) in float4 k
+ *   half spinor F16   uint4   [3][Vh], then float [Vh]  (4 complex as halves per uint4, divided
+ *                                             by the per-site scale that follows the halves)
+ *   full spinor       two half spinors, even parity first
+ *   nrhs spinors      nrhs consecutive fields
+ *   algebra field     double [2][4][8][Vh]    [parity][mu][a][cb]  (momenta, forces)
+ * Canonical layouts (for import/export only):
+ *   gauge    complex128 [V][4][3][3]          U_{x,mu}[row][col], x in lex order
+ *   spinor   complex128 [V][4][3] (full) or [Vh][4][3] (one parity, cb order)
+ *   algebra  float64 [V][4][8]
+ *
+ * Streams.  All work is enqueued on the context's HIP stream and is asynchronous unless the
+ * function returns a host scalar (solver statistics, actions, trajectory results), in which case
+ * it synchronises that stream before returning.
+ *
+ * Errors.  Every function returns a whmc_status; on failure whmc_last_error() holds a message
+ * for the calling thread.  Nothing aborts or throws across the ABI.  Unless noted, functions are
+ * not re-entrant on one context (one context = one stream of work).
+ */
+#ifndef WHMC_H
+#define WHMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WHMC_ABI_VERSION 1
+
+typedef enum whmc_status {
+  WHMC_OK = 0,
+  WHMC_EARG = 1,     /* bad argument: null pointer, odd extent, unknown enum, nrhs < 1, ... */
+  WHMC_EHIP = 2,     /* a HIP runtime call failed (message names it) */
+  WHMC_ENOCONV = 3,  /* solver hit maxiter; statistics are still filled in */
+  WHMC_EUNSUP = 4,   /* valid but unsupported combination (e.g. filter order k > 2) */
+  WHMC_ENOTSU3 = 5,  /* gauge field not unitary / det != 1 within the given tolerance */
+  WHMC_ESTATE = 6    /* call out of order (e.g. no gauge field loaded yet) */
+} whmc_status;
+
+typedef enum whmc_prec { WHMC_F64 = 0, WHMC_F32 = 1, WHMC_F16 = 2 } whmc_prec;
+typedef enum whmc_links { WHMC_L12 = 12, WHMC_L18 = 18 } whmc_links;
+typedef enum whmc_integrator { WHMC_LEAPFROG = 0, WHMC_OMELYAN = 1 } whmc_integrator;
+
+typedef struct whmc_ctx whmc_ctx;
+
+/* ------------------------------------------------------------------ context */
+
+int whmc_abi_version(void);
+const char* whmc_last_error(void);
+
+/* Create a context for a lattice of extents dims = {L_t, L_z, L_y, L_x} on HIP device `device`,
+ * enqueueing on `stream` (a hipStream_t; NULL = the default stream).  Allocates the gauge
+ * storage (~ V * 4 * 144 B in FP64 plus compressed copies on first use) and small scratch.
+ * EARG for odd or < 2 extents or V/2 >= 2^31. */
+whmc_status whmc_create(whmc_ctx** ctx, const int dims[4], int device, void* stream);
+void whmc_destroy(whmc_ctx* ctx);
+whmc_status whmc_set_stream(whmc_ctx* ctx, void* stream);
+
+/* Bytes of one field of the given kind in the whmc layout:
+ * kind 0 = half spinor, 1 = full spinor, 2 = algebra field (prec ignored), 3 = canonical gauge. */
+whmc_status whmc_field_bytes(const whmc_ctx* ctx, int kind, int prec, size_t* bytes);
+
+/* ------------------------------------------------------------------ gauge field (Sec. 1)
+ * Copy a canonical complex128 gauge field (device pointer) into the context.  The library keeps
+ * an FP64 18-real master copy and derives 12-real / FP32 / FP16 copies when an operator asks for
+ * them.  If unitarity_tol > 0 every link is checked: max |U U^dag - 1| and |det U - 1| must not
+ * exceed it, else ENOTSU3 (the field is still loaded; 12-real formats assume det = 1). */
+whmc_status whmc_load_gauge(whmc_ctx* ctx, const double* U, double unitarity_tol);
+whmc_status whmc_export_gauge(whmc_ctx* ctx, double* U);
+
+/* ------------------------------------------------------------------ layout conversion
+ * parity 0 / 1: one half field (canonical [Vh][4][3]); parity -1: full field (canonical [V][4][3]
+ * <-> two halves, even first).  nfields consecutive fields are converted. */
+whmc_status whmc_pack_spinor(whmc_ctx* ctx, double* dst, const double* src, int parity, int nfields);
+whmc_status whmc_unpack_spinor(whmc_ctx* ctx, double* dst, const double* src, int parity, int nfields);
+/* Convert nhalf half-spinor fields between precisions (both in whmc layout). */
+whmc_status whmc_convert_spinor(whmc_ctx* ctx, void* dst, int dst_prec, const void* src, int src_prec, int nhalf);
+/* canonical float64 [V][4][8] <-> whmc algebra layout */
+whmc_status whmc_pack_algebra(whmc_ctx* ctx, double* dst, const double* src);
+whmc_status whmc_unpack_algebra(whmc_ctx* ctx, double* dst, const double* src);
+
+/* ------------------------------------------------------------------ hopping matrix (Sec. 1, 2.2)
+ * out_parity p in {0, 1}: out (half field of parity p) = H_{p,1-p} in (half field of parity 1-p),
+ * i.e. H_eo for p = 0 and H_oe for p = 1; dagger = 1 applies the same block of H^dag.
+ * out_parity = -1: out (full) = H in (full), computed as both blocks.
+ * prec selects the spinor format of in/out, links the link format (F64 supports L18 and L12;
+ * F32 supports L18 and L12; F16 supports L12).  in and out must not overlap. */
+whmc_status whmc_apply_H(whmc_ctx* ctx, void* out, const void* in, int out_parity, int dagger, int prec, int links);
+
+/* out = M_oo in = in - kappa^2 H_oe H_eo in (dagger = 0) or M_oo^dag in (dagger = 1), FP64,
+ * odd-site half fields (Sec. 2.2).  Uses `tmp` (one even half field, FP64) as scratch if given,
+ * else context scratch. */
+whmc_status whmc_apply_Moo(whmc_ctx* ctx, double* out, const double* in, double kappa, int dagger);
+
+/* out_r = M_oo(kappa_r)^dag M_oo(kappa_r) in_r for r < nrhs, FP64, odd-site half fields. */
+whmc_status whmc_apply_MdagM(whmc_ctx* ctx, double* out, const double* in, const double* kappas, int nrhs);
+
+/* ------------------------------------------------------------------ solver (Sec. 1, 4)
+ * Solve M_oo(kappa_r)^dag M_oo(kappa_r) x_r = b_r (odd-site half fields, FP64 whmc layout) by CG
+ * from x_r = 0, until the true FP64 residual |b - A x| / |b| <= tol for every r.
+ *   prec = WHMC_F64: plain FP64 CG.
+ *   prec = WHMC_F32 / WHMC_F16: mixed precision; the Krylov bulk runs with spinors in that
+ *     format and `links`-real links of the same precision, FP64 reliable updates recompute
+ *     r = b - A x whenever the iterated residual drops below delta times its maximum since the
+ *     last update; dot products accumulate in FP64.
+ *   nrhs > 1: all right-hand sides advance together through multi-RHS kernels that load each
+ *     link once per block of rhs_block right-hand sides (0 = autotuned); a converged rhs is
+ *     frozen (masked) while the others continue.
+ * stats (may be NULL) receives nrhs entries.  Returns ENOCONV if any rhs misses tol. */
+typedef struct whmc_cg_params {
+  double tol;         /* target true relative residual, e.g. 1e-10 */
+  int maxiter;        /* per solve (counting sloppy iterations in mixed mode) */
+  int prec;           /* whmc_prec of the Krylov bulk */
+  int links;          /* whmc_links of the bulk operator */
+  double delta;       /* reliable-update trigger (mixed only), e.g. 0.1 */
+  int check_every;    /* iterations enqueued between host convergence checks (>= 1) */
+  int rhs_block;      /* multi-RHS register block, 0 = autotuned */
+} whmc_cg_params;
+
+typedef struct whmc_cg_stats {
+  int iters;             /* iterations (sloppy iterations in mixed mode) */
+  int reliable_updates;  /* FP64 residual recomputations (mixed mode) */
+  int converged;         /* 1 if the true residual reached tol */
+  double true_residual;  /* final |b - A x| / |b|, computed in FP64 */
+  double seconds;        /* wall time of the whole solve (all rhs) */
+} whmc_cg_stats;
+
+whmc_status whmc_cg_solve(whmc_ctx* ctx, double* x, const double* b, const double* kappas, int nrhs,
+                          const whmc_cg_params* params, whmc_cg_stats* stats);
+
+/* ------------------------------------------------------------------ filter, actions, forces
+ * Hopping-parameter-expansion filter (Sec. 2, 2.2): with K = kappa^2 H_oe H_eo,
+ *   M~ = M_oo exp(sum_{j<=k} K^j / j),  M~^{-1} = sum_n b_n K^n + alpha M_oo^{-1}.
+ * k = 0 is the plain action S_PF = |M_oo^{-1} phi|^2, k = 1 kappa^2-, k = 2 kappa^4-filtering.
+ * n_t truncates the force, n_max the action and the heat bath.  The gauge action becomes
+ * S_G at beta + 96 kappa^4 for k = 2 (Sec. 2; exact when no lattice extent is 2 or 4). */
+typedef struct whmc_filter {
+  int k;
+  int n_t;
+  int n_max;
+} whmc_filter;
+
+/* coefficient tables: b[0..n], c[0..n] (c_n = Taylor coefficients of exp(+sum_{j<=k} x^j/j),
+ * used by the heat bath phi = M~ eta) and alpha; computed on the host in extended precision. */
+whmc_status whmc_filter_coefficients(int k, int n, double* b, double* c, double* alpha);
+
+/* phi = M~ eta = M_oo sum_{n<=n_max} c_n K^n eta  (eq. initPseudo for M~), odd-site FP64. */
+whmc_status whmc_heatbath_phi(whmc_ctx* ctx, double* phi, const double* eta, const whmc_filter* f, double kappa);
+
+/* S_G (with the filter's beta shift) and S~_PF = |M~^{-1} phi|^2 at n_max; either output may be
+ * NULL to skip it.  solver may be NULL (FP64 CG to 1e-12). */
+whmc_status whmc_action(whmc_ctx* ctx, double* S_G, double* S_PF, const double* phi, const whmc_filter* f,
+                        double kappa, double beta, const whmc_cg_params* solver);
+
+/* plaquette <P> = sum_p Re Tr U_p / (3 N_p)  (Sec. 4.1), FP64, deterministic. */
+whmc_status whmc_plaquette(whmc_ctx* ctx, double* plaq);
+
+/* Forces in the whmc algebra layout, defined by (omega, F) = delta_omega S with
+ * delta U = omega U (Sec. 1).  flags: bit 0 pseudo-fermion force of S~_PF truncated at n_t
+ * (Sec. 2, Horner scheme), bit 1 gauge force of S_G at beta (+ the filter's shift),
+ * bit 2 accumulate into F instead of overwriting.  solver may be NULL (FP64 CG to 1e-12). */
+#define WHMC_FORCE_PF 1
+#define WHMC_FORCE_GAUGE 2
+#define WHMC_FORCE_ACCUMULATE 4
+whmc_status whmc_force(whmc_ctx* ctx, double* F, const double* phi, const whmc_filter* f, double kappa,
+                       double beta, const whmc_cg_params* solver, int flags);
+
+/* ------------------------------------------------------------------ HMC (Sec. 1, 4.1)
+ * One trajectory: phi = M~ eta, H0, molecular dynamics with Sexton-Weingarten levels (gauge on
+ * level 0 with m0 steps per coarse step, pseudo-fermion on level 1 with m steps over tau),
+ * H1, accept if u < exp(-dH).  The random inputs are passed in: pi0 (algebra layout, pi_a ~ N(0,1)),
+ * eta (odd-site FP64 spinor with density exp(-|eta|^2)), u uniform in [0,1).  On acceptance the
+ * context's gauge field becomes the new one, otherwise it is restored.  Steps: P(e): Pi -= e F,
+ * T(e): U = exp(e Pi) U; Omelyan with lambda, or leapfrog.  Consecutive P steps of one level that
+ * evaluate the force on the same field are merged. */
+typedef struct whmc_hmc_params {
+  double beta;
+  double kappa;
+  whmc_filter filter;
+  int integrator;   /* whmc_integrator */
+  double lambda;    /* Omelyan parameter, 1/6 in the paper */
+  int m;            /* coarse steps per trajectory */
+  int m0;           /* gauge steps per coarse (half) step */
+  double tau;       /* trajectory length */
+  whmc_cg_params md_solver;      /* solves inside the force */
+  whmc_cg_params action_solver;  /* solves for H0 / H1 */
+} whmc_hmc_params;
+
+typedef struct whmc_traj_result {
+  double dH, H0, H1;
+  int accepted;
+  double plaquette;       /* of the field kept after the accept/reject step */
+  long long cg_iters;     /* total solver iterations in the trajectory */
+  int n_solves;
+  double seconds;
+} whmc_traj_result;
+
+whmc_status whmc_hmc_trajectory(whmc_ctx* ctx, const whmc_hmc_params* p, const double* pi0, const double* eta,
+                                double u, whmc_traj_result* res);
+
+/* Molecular dynamics only: integrates the context's gauge field and pi (in place, algebra layout)
+ * over tau with phi fixed (for reversibility and dH-scaling studies). */
+whmc_status whmc_md_integrate(whmc_ctx* ctx, const whmc_hmc_params* p, double* pi, const double* phi);
+
+/* Hamiltonian H = (1/2)(Pi,Pi) + S~_G + S~_PF for the context's gauge field. */
+whmc_status whmc_hamiltonian(whmc_ctx* ctx, const whmc_hmc_params* p, const double* pi, const double* phi,
+                             double* H);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

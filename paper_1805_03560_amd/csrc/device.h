@@ -1,0 +1,365 @@
+// Device-side building blocks for the Wilson hot path on gfx950: complex and SU(3) arithmetic,
+// the storage formats of spinors and links in every precision, and checkerboard geometry.
+//
+// Storage (all structure-of-arrays over the V/2 sites of one parity, so that 64 consecutive
+// lanes of a wavefront touch 64 consecutive 8/16-byte words):
+//   spinor F64 : double2 [12][Vh]            component c = 3*spin + colour, one complex each
+//   spinor F32 : float4  [6][Vh]             two complex components per float4
+//   spinor F16 : uint4   [3][Vh] + float [Vh] four complex (8 halves) per uint4, values divided
+//                                             by the per-site scale (max |component|)
+//   link  F64-18 : double2 [2][4][9][Vh]     [parity of x][mu][row*3+col][cb(x)] holds U_{x,mu}
+//   link  F64-12 : double2 [2][4][6][Vh]     rows 0 and 1; row 2 = conj(row0 x row1)
+//   link  F32-12 : float4  [2][4][3][Vh]     rows 0,1 as 3 float4 (2 complex each)
+//   link  F16-12 : uint2   [2][4][3][Vh]     rows 0,1 as 3 x (4 halves = 2 complex)
+// Link entries are bounded by 1 in modulus, so half precision links need no scale.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#define WHMC_DEV __device__ __forceinline__
+
+namespace whmc {
+
+template <typename R>
+struct cplx {
+  R re, im;
+};
+
+template <typename R> WHMC_DEV cplx<R> mk(R a, R b) { return {a, b}; }
+template <typename R> WHMC_DEV cplx<R> operator+(cplx<R> a, cplx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R> WHMC_DEV cplx<R> operator-(cplx<R> a, cplx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R> WHMC_DEV cplx<R> operator-(cplx<R> a) { return {-a.re, -a.im}; }
+template <typename R> WHMC_DEV cplx<R> operator*(R s, cplx<R> a) { return {s * a.re, s * a.im}; }
+template <typename R> WHMC_DEV cplx<R> cmul(cplx<R> a, cplx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+template <typename R> WHMC_DEV cplx<R> cjmul(cplx<R> a, cplx<R> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename R> WHMC_DEV cplx<R> conj(cplx<R> a) { return {a.re, -a.im}; }
+template <typename R> WHMC_DEV cplx<R> times_i(cplx<R> a) { return {-a.im, a.re}; }
+template <typename R> WHMC_DEV cplx<R> times_mi(cplx<R> a) { return {a.im, -a.re}; }
+template <typename R> WHMC_DEV R norm2(cplx<R> a) { return a.re * a.re + a.im * a.im; }
+
+template <typename R>
+struct Spinor {
+  cplx<R> c[4][3];
+};
+template <typename R>
+struct HalfSpinor {
+  cplx<R> c[2][3];
+};
+template <typename R>
+struct SU3 {
+  cplx<R> e[3][3];
+};
+
+template <typename R> WHMC_DEV void zero(Spinor<R>& s) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) s.c[a][b] = {R(0), R(0)};
+}
+
+// y = U x   and   y = U^dag x   on a colour vector
+template <typename R> WHMC_DEV void mul(const SU3<R>& U, const cplx<R>* x, cplx<R>* y) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cplx<R> s = cmul(U.e[a][0], x[0]);
+    s = s + cmul(U.e[a][1], x[1]);
+    s = s + cmul(U.e[a][2], x[2]);
+    y[a] = s;
+  }
+}
+template <typename R> WHMC_DEV void mul_dag(const SU3<R>& U, const cplx<R>* x, cplx<R>* y) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cplx<R> s = cjmul(U.e[0][a], x[0]);
+    s = s + cjmul(U.e[1][a], x[1]);
+    s = s + cjmul(U.e[2][a], x[2]);
+    y[a] = s;
+  }
+}
+// third row of an SU(3) matrix from the first two: r2 = conj(r0 x r1)
+template <typename R> WHMC_DEV void reconstruct_row2(SU3<R>& U) {
+  U.e[2][0] = conj(cmul(U.e[0][1], U.e[1][2]) - cmul(U.e[0][2], U.e[1][1]));
+  U.e[2][1] = conj(cmul(U.e[0][2], U.e[1][0]) - cmul(U.e[0][0], U.e[1][2]));
+  U.e[2][2] = conj(cmul(U.e[0][0], U.e[1][1]) - cmul(U.e[0][1], U.e[1][0]));
+}
+
+// ------------------------------------------------------------------ geometry
+// dims L[0..3] = (L_t, L_z, L_y, L_x); direction mu is axis mu.  Checkerboard index
+// cb = lex / 2 with lex = ((t L_z + z) L_y + y) L_x + x.
+struct Geom {
+  int L[4];
+  int Vh;
+  int Lxh;   // L_x / 2
+};
+
+struct Coords {
+  int t, z, y, x, row, xh;
+};
+
+WHMC_DEV Coords coords_of(const Geom& g, int i, int par) {
+  Coords c;
+  c.row = i / g.Lxh;
+  c.xh = i - c.row * g.Lxh;
+  int tz = c.row / g.L[2];
+  c.y = c.row - tz * g.L[2];
+  c.t = tz / g.L[1];
+  c.z = tz - c.t * g.L[1];
+  c.x = 2 * c.xh + ((par + c.t + c.z + c.y) & 1);
+  return c;
+}
+
+// checkerboard index of the neighbour x + dir*mu_hat (dir = +1 / -1); also returns whether the
+// hop crosses the time boundary (fermion sign -1).
+template <int MU, int DIR>
+WHMC_DEV int neighbour(const Geom& g, const Coords& c, bool& wrap_t) {
+  wrap_t = false;
+  if (MU == 3) {
+    int x = c.x + DIR;
+    x = (x == g.L[3]) ? 0 : (x < 0 ? g.L[3] - 1 : x);
+    return c.row * g.Lxh + (x >> 1);
+  } else if (MU == 2) {
+    int y = c.y + DIR;
+    int d = DIR;
+    if (y == g.L[2]) d = 1 - g.L[2];
+    if (y < 0) d = g.L[2] - 1;
+    return (c.row + d) * g.Lxh + c.xh;
+  } else if (MU == 1) {
+    int z = c.z + DIR;
+    int d = DIR;
+    if (z == g.L[1]) d = 1 - g.L[1];
+    if (z < 0) d = g.L[1] - 1;
+    return (c.row + d * g.L[2]) * g.Lxh + c.xh;
+  } else {
+    int t = c.t + DIR;
+    int d = DIR;
+    if (t == g.L[0]) { d = 1 - g.L[0]; wrap_t = true; }
+    if (t < 0) { d = g.L[0] - 1; wrap_t = true; }
+    return (c.row + d * g.L[2] * g.L[1]) * g.Lxh + c.xh;
+  }
+}
+
+// ------------------------------------------------------------------ spinor storage
+struct SpinorF64 {
+  using Real = double;
+  double2* p;
+  int stride;
+  WHMC_DEV void load(int i, Spinor<double>& s) const {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      double2 v = p[(size_t)k * stride + i];
+      s.c[k / 3][k % 3] = {v.x, v.y};
+    }
+  }
+  WHMC_DEV void store(int i, const Spinor<double>& s) const {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) p[(size_t)k * stride + i] = make_double2(s.c[k / 3][k % 3].re, s.c[k / 3][k % 3].im);
+  }
+};
+
+struct SpinorF32 {
+  using Real = float;
+  float4* p;
+  int stride;
+  WHMC_DEV void load(int i, Spinor<float>& s) const {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      float4 v = p[(size_t)k * stride + i];
+      s.c[(2 * k) / 3][(2 * k) % 3] = {v.x, v.y};
+      s.c[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v.z, v.w};
+    }
+  }
+  WHMC_DEV void store(int i, const Spinor<float>& s) const {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      cplx<float> a = s.c[(2 * k) / 3][(2 * k) % 3], b = s.c[(2 * k + 1) / 3][(2 * k + 1) % 3];
+      p[(size_t)k * stride + i] = make_float4(a.re, a.im, b.re, b.im);
+    }
+  }
+};
+
+WHMC_DEV float h2f(unsigned short h) { return __half2float(__ushort_as_half(h)); }
+WHMC_DEV unsigned short f2h(float f) { return __half_as_ushort(__float2half_rn(f)); }
+
+struct SpinorF16 {
+  using Real = float;
+  uint4* p;
+  float* scale;
+  int stride;
+  WHMC_DEV void load(int i, Spinor<float>& s) const {
+    float sc = scale[i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint4 v = p[(size_t)k * stride + i];
+      unsigned int w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int comp = 4 * k + j;
+        s.c[comp / 3][comp % 3] = {sc * h2f((unsigned short)(w[j] & 0xffffu)), sc * h2f((unsigned short)(w[j] >> 16))};
+      }
+    }
+  }
+  WHMC_DEV void store(int i, const Spinor<float>& s) const {
+    float m = 0.f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) m = fmaxf(m, fmaxf(fabsf(s.c[a][b].re), fabsf(s.c[a][b].im)));
+    float inv = m > 0.f ? 1.0f / m : 0.f;
+    scale[i] = m;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      unsigned int w[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int comp = 4 * k + j;
+        w[j] = (unsigned int)f2h(inv * s.c[comp / 3][comp % 3].re) |
+               ((unsigned int)f2h(inv * s.c[comp / 3][comp % 3].im) << 16);
+      }
+      p[(size_t)k * stride + i] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  }
+};
+
+// ------------------------------------------------------------------ link storage
+// every link type: load(par, mu, i) -> U_{x,mu} for the site x of parity `par`, cb index i.
+struct LinkF64_18 {
+  using Real = double;
+  const double2* p;
+  int Vh;
+  WHMC_DEV void load(int par, int mu, int i, SU3<double>& U) const {
+    const double2* q = p + ((size_t)(par * 4 + mu) * 9) * Vh + i;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      double2 v = q[(size_t)k * Vh];
+      U.e[k / 3][k % 3] = {v.x, v.y};
+    }
+  }
+};
+
+struct LinkF64_12 {
+  using Real = double;
+  const double2* p;
+  int Vh;
+  WHMC_DEV void load(int par, int mu, int i, SU3<double>& U) const {
+    const double2* q = p + ((size_t)(par * 4 + mu) * 6) * Vh + i;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      double2 v = q[(size_t)k * Vh];
+      U.e[k / 3][k % 3] = {v.x, v.y};
+    }
+    reconstruct_row2(U);
+  }
+};
+
+struct LinkF32_12 {
+  using Real = float;
+  const float4* p;
+  int Vh;
+  WHMC_DEV void load(int par, int mu, int i, SU3<float>& U) const {
+    const float4* q = p + ((size_t)(par * 4 + mu) * 3) * Vh + i;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      float4 v = q[(size_t)k * Vh];
+      U.e[(2 * k) / 3][(2 * k) % 3] = {v.x, v.y};
+      U.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v.z, v.w};
+    }
+    reconstruct_row2(U);
+  }
+};
+
+struct LinkF32_18 {
+  using Real = float;
+  const float2* p;
+  int Vh;
+  WHMC_DEV void load(int par, int mu, int i, SU3<float>& U) const {
+    const float2* q = p + ((size_t)(par * 4 + mu) * 9) * Vh + i;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      float2 v = q[(size_t)k * Vh];
+      U.e[k / 3][k % 3] = {v.x, v.y};
+    }
+  }
+};
+
+struct LinkF16_12 {
+  using Real = float;
+  const uint2* p;
+  int Vh;
+  WHMC_DEV void load(int par, int mu, int i, SU3<float>& U) const {
+    const uint2* q = p + ((size_t)(par * 4 + mu) * 3) * Vh + i;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint2 v = q[(size_t)k * Vh];
+      U.e[(2 * k) / 3][(2 * k) % 3] = {h2f((unsigned short)(v.x & 0xffffu)), h2f((unsigned short)(v.x >> 16))};
+      U.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {h2f((unsigned short)(v.y & 0xffffu)), h2f((unsigned short)(v.y >> 16))};
+    }
+    reconstruct_row2(U);
+  }
+};
+
+// ------------------------------------------------------------------ reductions
+// wavefront (64 lanes) then workgroup sum; result valid in thread 0.
+template <int BLOCK>
+WHMC_DEV double block_sum(double v, double* lds) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < BLOCK / 64; ++w) s += lds[w];
+  }
+  return s;
+}
+
+struct Reduce {
+  double* partials;    // per-block partial sums
+  unsigned* counter;   // last-block-done counter (reset by the last block)
+  double* result;      // final sums
+};
+
+// ------------------------------------------------------------------ grid-wide FP64 sums
+// Each block writes its partial sum; the last block to finish (atomic counter) adds the partials
+// in a fixed order, so the result is deterministic, and resets the counter.
+// Grid-wide FP64 sum: each block writes its partial; the last block to finish (atomic counter)
+// adds the partials in a fixed order -- so the result is deterministic -- resets the counter and
+// hands the total to fin(total) in its thread 0.  Every thread of the grid must call this.
+template <int BLOCK, class Fin>
+WHMC_DEV void grid_sum_then(double v, const Reduce& red, Fin fin) {
+  __shared__ double lds[BLOCK / 64];
+  __shared__ int last;
+  double s = block_sum<BLOCK>(v, lds);
+  if (threadIdx.x == 0) {
+    red.partials[blockIdx.x] = s;
+    __threadfence();
+    unsigned prev = atomicAdd(red.counter, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    double t = 0.0;
+    for (int k = threadIdx.x; k < (int)gridDim.x; k += BLOCK) t += red.partials[k];
+    __syncthreads();
+    t = block_sum<BLOCK>(t, lds);
+    if (threadIdx.x == 0) {
+      *red.counter = 0u;
+      fin(t);
+    }
+  }
+}
+
+template <int BLOCK>
+WHMC_DEV void grid_sum(double v, const Reduce& red, double* out) {
+  grid_sum_then<BLOCK>(v, red, [=](double t) { *out = t; });
+}
+
+}  // namespace whmc

@@ -1,0 +1,134 @@
+// Host-side internals shared by the translation units of libwhmc: the context, error reporting,
+// scratch management and the launchers each .hip file exports to the others.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/whmc.h"
+#include "device.h"
+
+namespace whmc {
+
+void set_error(const std::string& msg);
+
+#define WHMC_HIP(call)                                                                         \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) {                                                                    \
+      ::whmc::set_error(std::string(#call) + " failed: " + hipGetErrorString(e_) + " at " +    \
+                        __FILE__ + ":" + std::to_string(__LINE__));                            \
+      return WHMC_EHIP;                                                                        \
+    }                                                                                          \
+  } while (0)
+
+#define WHMC_CHECK(cond, code, msg) \
+  do {                              \
+    if (!(cond)) {                  \
+      ::whmc::set_error(msg);       \
+      return code;                  \
+    }                               \
+  } while (0)
+
+#define WHMC_TRY(expr)              \
+  do {                              \
+    whmc_status s_ = (expr);        \
+    if (s_ != WHMC_OK) return s_;   \
+  } while (0)
+
+constexpr int kBlock = 256;
+
+// per-solve scalar state that lives on the device so that iterations can be enqueued without a
+// host round trip; `done` / `pause` make the remaining queued kernels exit at once.
+struct CGScalars {
+  double rr;        // |r|^2 of the current residual
+  double pAp;       // (p, A p)
+  double alpha, beta;
+  double rr_old;    // |r|^2 before the last update (reliable-update restart of p)
+  double stop_rr;   // convergence threshold on |r|^2
+  double rmax2;     // mixed precision: max |r|^2 since the last reliable update
+  double delta2;    // mixed precision: reliable update when |r|^2 < delta2 * rmax2
+  int done;         // converged (or broken down)
+  int pause;        // mixed precision: reliable update requested
+  int iter;         // iterations completed
+  int active;       // multi-RHS: 1 while the rhs still iterates
+};
+
+constexpr int kMaxRhs = 16;
+
+}  // namespace whmc
+
+struct whmc_ctx {
+  int dims[4];
+  long long V;
+  int Vh;
+  whmc::Geom g;
+  int device;
+  hipStream_t stream;
+  // gauge field copies
+  double2* U18 = nullptr;          // master FP64 18-real
+  double2* U12 = nullptr;          // FP64 12-real
+  float2* U32_18 = nullptr;
+  float4* U32_12 = nullptr;
+  uint2* U16_12 = nullptr;
+  bool gauge_loaded = false;
+  bool derived_valid[4] = {false, false, false, false};  // U12, U32_18, U32_12, U16_12
+  // scratch
+  std::map<std::string, std::pair<void*, size_t>> ws;
+  whmc::Reduce red{};
+  whmc::CGScalars* scal = nullptr;   // kMaxRhs entries
+  whmc::CGScalars* scal_host = nullptr;  // pinned mirror
+  double* host_pinned = nullptr;     // small pinned buffer for scalar read-back
+  int num_blocks() const { return (Vh + whmc::kBlock - 1) / whmc::kBlock; }
+};
+
+namespace whmc {
+
+// scratch buffer owned by the context, grown on demand, freed in whmc_destroy
+whmc_status workspace(whmc_ctx* c, const std::string& name, size_t bytes, void** out);
+
+// ---- gauge copies (core.hip)
+whmc_status ensure_links(whmc_ctx* c, int prec, int links);
+whmc_status gauge_changed(whmc_ctx* c);   // invalidate derived copies after the master changed
+
+// ---- hopping matrix launchers (core.hip).  All operate on half fields in whmc layout.
+// out = a * x + b * H_{par,1-par}^{(dag)} in   (x may be null: then out = b * H in)
+// if norm_out != null the FP64 sum |out|^2 is written there (device pointer).
+whmc_status hop(whmc_ctx* c, int prec, int links, int par, int dag, void* out, const void* in, const void* x,
+                double a, double b, double* norm_out);
+
+// ---- FP64 BLAS on half fields (core.hip); n = number of half fields
+whmc_status axpby_f64(whmc_ctx* c, double* y, double a, const double* x, double b, int nhalf);  // y = a x + b y
+whmc_status copy_f64(whmc_ctx* c, double* y, const double* x, int nhalf);
+whmc_status gamma5_f64(whmc_ctx* c, double* y, const double* x, int nhalf);
+whmc_status norm2_f64(whmc_ctx* c, const double* x, int nhalf, double* dev_out);      // async, device result
+whmc_status dot_re_f64(whmc_ctx* c, const double* x, const double* y, int nhalf, double* dev_out);
+whmc_status read_scalar(whmc_ctx* c, const double* dev, double* host);                // synchronises
+whmc_status convert_spinor(whmc_ctx* c, void* dst, int dst_prec, const void* src, int src_prec, int nhalf);
+whmc_status zero_bytes(whmc_ctx* c, void* p, size_t bytes);   // fill kernel (graph-safe)
+
+// ---- operators composed from hops (core.hip)
+whmc_status apply_Moo_f64(whmc_ctx* c, double* out, const double* in, double kappa, int dagger, double* tmp_even);
+whmc_status apply_MdagM_f64(whmc_ctx* c, double* out, const double* in, double kappa, double* tmp_even,
+                            double* tmp_odd);
+whmc_status apply_K_f64(whmc_ctx* c, double* out, const double* in, double kappa, int dagger, double* even_out,
+                        const double* x, double a);   // out = a x + K^(dag) in; even_out = H_eo^(dag) in
+
+// ---- solvers (cg.hip)
+whmc_status cg_solve(whmc_ctx* c, double* x, const double* b, const double* kappas, int nrhs,
+                     const whmc_cg_params* p, whmc_cg_stats* st);
+
+// ---- gauge and force kernels (gauge.hip)
+whmc_status plaquette_sum(whmc_ctx* c, double* host_out);
+whmc_status gauge_force(whmc_ctx* c, double* F, double beta_eff, double scale, int accumulate);
+whmc_status pf_force_pairs(whmc_ctx* c, double* F, const double* const* X_e, const double* const* X_o,
+                           const double* const* Y_e, const double* const* Y_o, int npairs, double kappa_eff,
+                           int accumulate);
+whmc_status mom_update(whmc_ctx* c, double* pi, const double* F, double eps);   // pi -= eps F
+whmc_status link_update(whmc_ctx* c, const double* pi, double eps);              // U = exp(eps pi) U
+whmc_status algebra_norm2(whmc_ctx* c, const double* pi, double* host_out);
+whmc_status pack_algebra(whmc_ctx* c, double* dst, const double* src, int unpack);
+
+}  // namespace whmc

@@ -1,0 +1,312 @@
+"""Thin Python binding of libwhmc (the C ABI in include/whmc.h).
+
+Argument marshalling only: every step of the computation runs in the HIP library.  Fields are
+torch tensors on the context's GPU (PyTorch supplies device memory and the stream); the library
+is called on torch's current stream so that torch and library work stay ordered.
+
+Layouts (see include/whmc.h): canonical complex128 tensors for import/export, and the library's
+structure-of-arrays "whmc layout" for everything the hot path touches.  ``half_spinor()`` etc.
+allocate correctly sized whmc-layout buffers.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwhmc.so")
+
+F64, F32, F16 = 0, 1, 2
+L12, L18 = 12, 18
+LEAPFROG, OMELYAN = 0, 1
+FORCE_PF, FORCE_GAUGE, FORCE_ACCUMULATE = 1, 2, 4
+_STATUS = {0: "OK", 1: "EARG", 2: "EHIP", 3: "ENOCONV", 4: "EUNSUP", 5: "ENOTSU3", 6: "ESTATE"}
+_HALF_BYTES = {F64: 192, F32: 96, F16: 52}
+
+
+class WhmcError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"whmc {_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class CGParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("prec", ctypes.c_int),
+                ("links", ctypes.c_int), ("delta", ctypes.c_double), ("check_every", ctypes.c_int),
+                ("rhs_block", ctypes.c_int)]
+
+
+class CGStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int), ("converged", ctypes.c_int),
+                ("true_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Filter(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("n_t", ctypes.c_int), ("n_max", ctypes.c_int)]
+
+
+class HMCParams(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("kappa", ctypes.c_double), ("filter", Filter),
+                ("integrator", ctypes.c_int), ("lam", ctypes.c_double), ("m", ctypes.c_int), ("m0", ctypes.c_int),
+                ("tau", ctypes.c_double), ("md_solver", CGParams), ("action_solver", CGParams)]
+
+
+class TrajResult(ctypes.Structure):
+    _fields_ = [("dH", ctypes.c_double), ("H0", ctypes.c_double), ("H1", ctypes.c_double),
+                ("accepted", ctypes.c_int), ("plaquette", ctypes.c_double), ("cg_iters", ctypes.c_longlong),
+                ("n_solves", ctypes.c_int), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def cg_params(tol=1e-10, maxiter=10000, prec=F64, links=L18, delta=0.1, check_every=8, rhs_block=0):
+    return CGParams(tol, maxiter, prec, links, delta, check_every, rhs_block)
+
+
+_lib = None
+_P = ctypes.c_void_p
+_SIGS = {
+    "whmc_abi_version": ([], ctypes.c_int),
+    "whmc_last_error": ([], ctypes.c_char_p),
+    "whmc_create": ([ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int), ctypes.c_int, _P], ctypes.c_int),
+    "whmc_destroy": ([_P], None),
+    "whmc_set_stream": ([_P, _P], ctypes.c_int),
+    "whmc_field_bytes": ([_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "whmc_load_gauge": ([_P, _P, ctypes.c_double], ctypes.c_int),
+    "whmc_export_gauge": ([_P, _P], ctypes.c_int),
+    "whmc_pack_spinor": ([_P, _P, _P, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "whmc_unpack_spinor": ([_P, _P, _P, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "whmc_convert_spinor": ([_P, _P, ctypes.c_int, _P, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "whmc_pack_algebra": ([_P, _P, _P], ctypes.c_int),
+    "whmc_unpack_algebra": ([_P, _P, _P], ctypes.c_int),
+    "whmc_apply_H": ([_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "whmc_apply_Moo": ([_P, _P, _P, ctypes.c_double, ctypes.c_int], ctypes.c_int),
+    "whmc_apply_MdagM": ([_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int], ctypes.c_int),
+    "whmc_cg_solve": ([_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.POINTER(CGParams),
+                       ctypes.POINTER(CGStats)], ctypes.c_int),
+    "whmc_filter_coefficients": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "whmc_heatbath_phi": ([_P, _P, _P, ctypes.POINTER(Filter), ctypes.c_double], ctypes.c_int),
+    "whmc_action": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _P,
+                     ctypes.POINTER(Filter), ctypes.c_double, ctypes.c_double, ctypes.POINTER(CGParams)],
+                    ctypes.c_int),
+    "whmc_plaquette": ([_P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "whmc_force": ([_P, _P, _P, ctypes.POINTER(Filter), ctypes.c_double, ctypes.c_double,
+                    ctypes.POINTER(CGParams), ctypes.c_int], ctypes.c_int),
+    "whmc_hmc_trajectory": ([_P, ctypes.POINTER(HMCParams), _P, _P, ctypes.c_double, ctypes.POINTER(TrajResult)],
+                            ctypes.c_int),
+    "whmc_md_integrate": ([_P, ctypes.POINTER(HMCParams), _P, _P], ctypes.c_int),
+    "whmc_hamiltonian": ([_P, ctypes.POINTER(HMCParams), _P, _P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+}
+
+
+def lib():
+    """load libwhmc.so; raises if the library has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1805_03560_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise WhmcError(status, lib().whmc_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to whmc must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def filter_coefficients(k, n):
+    b = (ctypes.c_double * (n + 1))()
+    c = (ctypes.c_double * (n + 1))()
+    a = ctypes.c_double()
+    _check(lib().whmc_filter_coefficients(k, n, b, c, ctypes.byref(a)))
+    return list(b), list(c), a.value
+
+
+class Context:
+    """one lattice on one GPU; wraps a whmc_ctx."""
+
+    def __init__(self, dims, device=0, stream=None):
+        self.dims = tuple(int(d) for d in dims)
+        self.V = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
+        self.Vh = self.V // 2
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = _P()
+        arr = (ctypes.c_int * 4)(*self.dims)
+        _check(lib().whmc_create(ctypes.byref(h), arr, device, _P(stream.cuda_stream)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().whmc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ buffers
+    def half_spinor(self, prec=F64, n=1):
+        nbytes = _HALF_BYTES[prec] * self.Vh * n
+        if prec == F64:
+            return torch.zeros(n * 24 * self.Vh, dtype=torch.float64, device=self.device)
+        if prec == F32:
+            return torch.zeros(n * 24 * self.Vh, dtype=torch.float32, device=self.device)
+        return torch.zeros(nbytes, dtype=torch.uint8, device=self.device)
+
+    def full_spinor(self, prec=F64):
+        return self.half_spinor(prec, 2)
+
+    def algebra(self):
+        return torch.zeros(self.V * 32, dtype=torch.float64, device=self.device)
+
+    def _dev(self, t, name):
+        if t.device != self.device:
+            raise ValueError(f"{name} must be on {self.device}")
+        return t
+
+    # ------------------------------------------------------------ gauge field
+    def load_gauge(self, U, unitarity_tol=1e-12):
+        U = self._dev(U, "U").contiguous()
+        if U.dtype != torch.complex128 or tuple(U.shape) != self.dims + (4, 3, 3):
+            raise ValueError("U must be complex128 of shape (L_t, L_z, L_y, L_x, 4, 3, 3)")
+        _check(lib().whmc_load_gauge(self._h, _ptr(U), unitarity_tol))
+
+    def export_gauge(self):
+        U = torch.empty(self.dims + (4, 3, 3), dtype=torch.complex128, device=self.device)
+        _check(lib().whmc_export_gauge(self._h, _ptr(U)))
+        return U
+
+    # ------------------------------------------------------------ layouts
+    def pack_spinor(self, psi, parity):
+        """canonical complex128 (Vh,4,3) [parity 0/1] or (V,4,3)/(dims,4,3) [parity -1], optionally
+        with a leading field axis -> whmc layout float64 buffer."""
+        psi = self._dev(psi, "psi").contiguous()
+        n_sites = self.V if parity < 0 else self.Vh
+        nf = psi.numel() // (12 * n_sites)
+        out = torch.empty(nf * n_sites * 24, dtype=torch.float64, device=self.device)
+        _check(lib().whmc_pack_spinor(self._h, _ptr(out), _ptr(torch.view_as_real(psi)), parity, nf))
+        return out
+
+    def unpack_spinor(self, buf, parity, nfields=1):
+        n_sites = self.V if parity < 0 else self.Vh
+        out = torch.empty((nfields, n_sites, 4, 3) if nfields > 1 else (n_sites, 4, 3), dtype=torch.complex128,
+                          device=self.device)
+        _check(lib().whmc_unpack_spinor(self._h, _ptr(torch.view_as_real(out)), _ptr(buf), parity, nfields))
+        return out
+
+    def convert_spinor(self, src, src_prec, dst_prec, nhalf=1):
+        dst = self.half_spinor(dst_prec, nhalf)
+        _check(lib().whmc_convert_spinor(self._h, _ptr(dst), dst_prec, _ptr(src), src_prec, nhalf))
+        return dst
+
+    def pack_algebra(self, a):
+        a = self._dev(a, "a").contiguous()
+        out = torch.empty(self.V * 32, dtype=torch.float64, device=self.device)
+        _check(lib().whmc_pack_algebra(self._h, _ptr(out), _ptr(a)))
+        return out
+
+    def unpack_algebra(self, buf):
+        out = torch.empty(self.dims + (4, 8), dtype=torch.float64, device=self.device)
+        _check(lib().whmc_unpack_algebra(self._h, _ptr(out), _ptr(buf)))
+        return out
+
+    # ------------------------------------------------------------ operators
+    def apply_H(self, inp, out_parity, dagger=False, prec=F64, links=L18, out=None):
+        if out is None:
+            out = self.half_spinor(prec, 2 if out_parity < 0 else 1)
+        _check(lib().whmc_apply_H(self._h, _ptr(out), _ptr(inp), out_parity, int(dagger), prec, links))
+        return out
+
+    def apply_Moo(self, inp, kappa, dagger=False, out=None):
+        out = self.half_spinor() if out is None else out
+        _check(lib().whmc_apply_Moo(self._h, _ptr(out), _ptr(inp), kappa, int(dagger)))
+        return out
+
+    def apply_MdagM(self, inp, kappas, out=None):
+        kappas = [float(k) for k in (kappas if hasattr(kappas, "__len__") else [kappas])]
+        n = len(kappas)
+        out = self.half_spinor(F64, n) if out is None else out
+        _check(lib().whmc_apply_MdagM(self._h, _ptr(out), _ptr(inp), (ctypes.c_double * n)(*kappas), n))
+        return out
+
+    def cg_solve(self, b, kappas, params=None, x=None, raise_on_noconv=True):
+        kappas = [float(k) for k in (kappas if hasattr(kappas, "__len__") else [kappas])]
+        n = len(kappas)
+        params = params or cg_params()
+        x = self.half_spinor(F64, n) if x is None else x
+        stats = (CGStats * n)()
+        rc = lib().whmc_cg_solve(self._h, _ptr(x), _ptr(b), (ctypes.c_double * n)(*kappas), n, ctypes.byref(params),
+                                 stats)
+        if rc != 0 and (rc != 3 or raise_on_noconv):
+            _check(rc)
+        return x, [s.as_dict() for s in stats]
+
+    # ------------------------------------------------------------ actions, forces, HMC
+    def heatbath_phi(self, eta, k, n_t, n_max, kappa):
+        phi = self.half_spinor()
+        f = Filter(k, n_t, n_max)
+        _check(lib().whmc_heatbath_phi(self._h, _ptr(phi), _ptr(eta), ctypes.byref(f), kappa))
+        return phi
+
+    def action(self, phi, k, n_t, n_max, kappa, beta, solver=None):
+        sg, spf = ctypes.c_double(), ctypes.c_double()
+        f = Filter(k, n_t, n_max)
+        _check(lib().whmc_action(self._h, ctypes.byref(sg), ctypes.byref(spf), _ptr(phi), ctypes.byref(f), kappa,
+                                 beta, ctypes.byref(solver) if solver is not None else None))
+        return sg.value, spf.value
+
+    def plaquette(self):
+        p = ctypes.c_double()
+        _check(lib().whmc_plaquette(self._h, ctypes.byref(p)))
+        return p.value
+
+    def force(self, phi, k, n_t, n_max, kappa, beta, flags=FORCE_PF, solver=None, out=None):
+        out = self.algebra() if out is None else out
+        f = Filter(k, n_t, n_max)
+        _check(lib().whmc_force(self._h, _ptr(out), _ptr(phi), ctypes.byref(f), kappa, beta,
+                                ctypes.byref(solver) if solver is not None else None, flags))
+        return out
+
+    def hmc_trajectory(self, params, pi0, eta, u):
+        res = TrajResult()
+        _check(lib().whmc_hmc_trajectory(self._h, ctypes.byref(params), _ptr(pi0), _ptr(eta), float(u),
+                                         ctypes.byref(res)))
+        return res.as_dict()
+
+    def md_integrate(self, params, pi, phi):
+        _check(lib().whmc_md_integrate(self._h, ctypes.byref(params), _ptr(pi), _ptr(phi)))
+        return pi
+
+    def hamiltonian(self, params, pi, phi):
+        h = ctypes.c_double()
+        _check(lib().whmc_hamiltonian(self._h, ctypes.byref(params), _ptr(pi), _ptr(phi), ctypes.byref(h)))
+        return h.value
+
+
+def hmc_params(beta=5.6, kappa=0.156, k=0, n_t=0, n_max=0, integrator=OMELYAN, lam=1.0 / 6.0, m=10, m0=4, tau=1.0,
+               md_solver=None, action_solver=None):
+    return HMCParams(beta, kappa, Filter(k, n_t, n_max), integrator, lam, m, m0, tau,
+                     md_solver or cg_params(tol=1e-12), action_solver or cg_params(tol=1e-12))

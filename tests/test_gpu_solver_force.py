@@ -1,0 +1,155 @@
+"""GPU parity of the solvers, actions, forces and the HMC trajectory against the oracle.
+
+Tolerances: operator applications 1e-12 relative; solves are run to 1e-13/1e-14 on both sides,
+so solutions agree to ~cond(A) x 1e-13 (cond ~ 10-100 on these fields); forces that go through
+solves to 1e-10 relative; mixed-precision solves must reach the same 1e-10 true FP64 residual."""
+import numpy as np
+import pytest
+
+from oracle import dirac, force, gauge, hmc, hpe
+from oracle.lattice import Lattice
+from oracle.solve import cg
+from paper_1805_03560_amd import synth, whmc
+
+from gpu_util import algebra_to_numpy, make_ctx, pack_half, rel_err, to_dev, unpack_half
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dims,gen", [((4, 4, 4, 4), "haar"), ((8, 4, 4, 8), "smooth")])
+def test_cg_fp64_parity(dims, gen):
+    lat = Lattice(dims)
+    U = synth.haar_links(dims, 2000) if gen == "haar" else synth.smooth_links(dims, 2000)
+    b = synth.gaussian_spinor(lat.Vh, 0)
+    kappa = 0.156
+    ref, _, _ = cg(lambda v: dirac.apply_MooDagMoo(lat, U, v, kappa), b, tol=1e-14)
+    ctx = make_ctx(dims, U)
+    x, st = ctx.cg_solve(pack_half(ctx, b), [kappa], whmc.cg_params(tol=1e-13, check_every=4))
+    assert st[0]["converged"] and st[0]["true_residual"] <= 1e-13
+    assert rel_err(unpack_half(ctx, x), ref) < 1e-11
+    # at the 1e-10 tolerance of the workloads: error bounded by cond x 1e-10
+    x, st = ctx.cg_solve(pack_half(ctx, b), [kappa], whmc.cg_params(tol=1e-10))
+    assert st[0]["true_residual"] <= 1e-10
+    assert rel_err(unpack_half(ctx, x), ref) < 1e-8
+
+
+@pytest.mark.parametrize("prec,links", [(whmc.F32, whmc.L12), (whmc.F32, whmc.L18), (whmc.F16, whmc.L12)])
+def test_mixed_cg_reaches_fp64_residual(prec, links):
+    dims = (8, 4, 4, 8)
+    lat = Lattice(dims)
+    U = synth.smooth_links(dims, 2010)
+    b = synth.gaussian_spinor(lat.Vh, 2011)
+    kappa = 0.1575
+    ref, _, _ = cg(lambda v: dirac.apply_MooDagMoo(lat, U, v, kappa), b, tol=1e-14)
+    ctx = make_ctx(dims, U)
+    x, st = ctx.cg_solve(pack_half(ctx, b), [kappa], whmc.cg_params(tol=1e-10, prec=prec, links=links, delta=0.1))
+    assert st[0]["converged"] and st[0]["true_residual"] <= 1e-10
+    assert st[0]["reliable_updates"] >= 1
+    assert rel_err(unpack_half(ctx, x), ref) < 1e-8
+
+
+def test_multi_rhs_cg_parity():
+    dims = (4, 4, 4, 8)
+    lat = Lattice(dims)
+    U = synth.smooth_links(dims, 2020)
+    kappas = [0.150, 0.153, 0.156, 0.1575]
+    bs = np.stack([synth.gaussian_spinor(lat.Vh, 4000 + r) for r in range(4)])
+    ctx = make_ctx(dims, U)
+    x, st = ctx.cg_solve(pack_half(ctx, bs), kappas, whmc.cg_params(tol=1e-12))
+    got = unpack_half(ctx, x, 4)
+    for r, k in enumerate(kappas):
+        ref, _, _ = cg(lambda v: dirac.apply_MooDagMoo(lat, U, v, k), bs[r], tol=1e-14)
+        assert st[r]["true_residual"] <= 1e-12
+        assert rel_err(got[r], ref) < 1e-9
+
+
+def test_plaquette_and_gauge_force_parity():
+    dims = (4, 4, 6, 6)
+    lat = Lattice(dims)
+    U = synth.smooth_links(dims, 2030)
+    ctx = make_ctx(dims, U)
+    assert ctx.plaquette() == pytest.approx(gauge.plaquette(lat, U), rel=1e-13)
+    F = ctx.force(ctx.half_spinor(), 0, 0, 0, 0.156, 5.6, flags=whmc.FORCE_GAUGE)
+    assert rel_err(algebra_to_numpy(ctx, F), gauge.gauge_force(lat, U, 5.6)) < 1e-12
+    # kappa^4 filtering shifts beta by 96 kappa^4
+    sg, _ = ctx.action(ctx.half_spinor(), 2, 0, 0, 0.156, 5.6)
+    assert sg == pytest.approx(gauge.gauge_action(lat, U, 5.6 + 96 * 0.156 ** 4), rel=1e-13)
+
+
+@pytest.mark.parametrize("k,n_t,n_max", [(0, 0, 0), (1, 5, 19), (2, 7, 29), (2, 0, 12)])
+def test_filtered_action_force_heatbath_parity(k, n_t, n_max):
+    dims = (4, 4, 4, 4)
+    lat = Lattice(dims)
+    U = synth.haar_links(dims, 2040 + k)
+    kappa = 0.156
+    eta = synth.gaussian_spinor(lat.Vh, 2050)
+    ctx = make_ctx(dims, U)
+    solver = whmc.cg_params(tol=1e-14, check_every=4)
+    phi_ref = hpe.heatbath_phi(lat, U, eta, kappa, k, n_max)
+    phi = ctx.heatbath_phi(pack_half(ctx, eta), k, n_t, n_max, kappa)
+    assert rel_err(unpack_half(ctx, phi), phi_ref) < 1e-12
+    phi_b = pack_half(ctx, phi_ref)
+    _, spf = ctx.action(phi_b, k, n_t, n_max, kappa, 5.6, solver=solver)
+    assert spf == pytest.approx(hpe.filtered_action(lat, U, phi_ref, kappa, k, n_max, tol=1e-14), rel=1e-11)
+    F = ctx.force(phi_b, k, n_t, n_max, kappa, 5.6, flags=whmc.FORCE_PF, solver=solver)
+    ref = hpe.filtered_force(lat, U, phi_ref, kappa, k, n_t, tol=1e-14)
+    assert rel_err(algebra_to_numpy(ctx, F), ref) < 1e-10
+
+
+def test_unfiltered_force_matches_plain_eo_force():
+    dims = (4, 2, 2, 4)
+    lat = Lattice(dims)
+    U = synth.haar_links(dims, 2060)
+    kappa = 0.15
+    phi = synth.gaussian_spinor(lat.Vh, 2061)
+    ctx = make_ctx(dims, U)
+    F = ctx.force(pack_half(ctx, phi), 0, 0, 0, kappa, 5.6, solver=whmc.cg_params(tol=1e-14))
+    assert rel_err(algebra_to_numpy(ctx, F), force.pf_force_eo(lat, U, phi, kappa, tol=1e-14)) < 1e-10
+
+
+@pytest.mark.parametrize("integrator,k,n_t,n_max", [("leapfrog", 0, 0, 0), ("omelyan", 2, 5, 12)])
+def test_hmc_trajectory_parity(integrator, k, n_t, n_max):
+    dims = (4, 2, 2, 4)
+    lat = Lattice(dims)
+    U = synth.smooth_links(dims, 2070)
+    pi = synth.gaussian_momenta(dims, 2071)
+    eta = synth.gaussian_spinor(lat.Vh, 2072)
+    p = hmc.HMCParams(beta=5.6, kappa=0.15, k=k, n_t=n_t, n_max=n_max, integrator=integrator, m=3, m0=2, tau=0.5,
+                      tol=1e-14)
+    ref = hmc.trajectory(lat, U, pi, eta, 0.5, p)
+    ctx = make_ctx(dims, U)
+    solver = whmc.cg_params(tol=1e-14, check_every=4)
+    wp = whmc.hmc_params(beta=5.6, kappa=0.15, k=k, n_t=n_t, n_max=n_max,
+                         integrator=whmc.OMELYAN if integrator == "omelyan" else whmc.LEAPFROG, m=3, m0=2, tau=0.5,
+                         md_solver=solver, action_solver=solver)
+    res = ctx.hmc_trajectory(wp, ctx.pack_algebra(to_dev(pi)), pack_half(ctx, eta), 0.5)
+    assert res["H0"] == pytest.approx(ref["H0"], rel=1e-12)
+    assert res["dH"] == pytest.approx(ref["dH"], abs=1e-8)
+    assert bool(res["accepted"]) == ref["accepted"]
+    U_gpu = ctx.export_gauge().cpu().numpy()
+    assert rel_err(U_gpu, ref["U"]) < 1e-10
+
+
+def test_md_reversibility_and_dtau_scaling():
+    dims = (4, 4, 4, 4)
+    lat = Lattice(dims)
+    U = synth.smooth_links(dims, 2080)
+    pi0 = synth.gaussian_momenta(dims, 2081)
+    eta = synth.gaussian_spinor(lat.Vh, 2082)
+    solver = whmc.cg_params(tol=1e-14, check_every=4)
+    ctx = make_ctx(dims, U)
+    dHs = []
+    for m in (2, 4, 8):
+        wp = whmc.hmc_params(beta=5.6, kappa=0.15, k=1, n_t=6, n_max=6, integrator=whmc.OMELYAN, m=m, m0=2, tau=0.5,
+                             md_solver=solver, action_solver=solver)
+        ctx.load_gauge(to_dev(U))
+        phi = ctx.heatbath_phi(pack_half(ctx, eta), 1, 6, 6, 0.15)
+        pi = ctx.pack_algebra(to_dev(pi0))
+        H0 = ctx.hamiltonian(wp, pi, phi)
+        ctx.md_integrate(wp, pi, phi)
+        dHs.append(ctx.hamiltonian(wp, pi, phi) - H0)
+        if m == 4:
+            ctx.md_integrate(wp, -pi, phi)   # flip momenta and integrate back
+            delta = float(np.sum(np.abs(ctx.export_gauge().cpu().numpy() - U) ** 2))
+            assert delta < 1e-20
+    assert 3.0 < dHs[0] / dHs[1] < 5.5 and 3.3 < dHs[1] / dHs[2] < 4.8, dHs
