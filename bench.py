@@ -41,6 +41,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed apply_H region")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a device copy of 2 GiB (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
@@ -54,6 +56,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 3 copies of 2 GiB")
+        return
     T, Z, Y, X = DIMS
     V = T * Z * Y * X
     Vh = V // 2
@@ -159,8 +169,9 @@ def extras(ctx, whmc, torch, np, stream, Vh):
     # CG to 1e-10: FP64 vs mixed precision (32^3 x 64, kappa = 0.1575)
     b = ctx.pack_spinor(torch.from_numpy(synth.gaussian_spinor(Vh, 3003)).to(ctx.device), 0)
     cgr = {}
-    x64s, st = ctx.cg_solve(b, [KAPPA], whmc.cg_params(tol=1e-10))      # warm (workspace allocation)
-    ref = x64s.clone()
+    # reference solution: FP64 CG to a true residual of 1e-13
+    ref, st = ctx.cg_solve(b, [KAPPA], whmc.cg_params(tol=1e-13))
+    ref = ref.clone()
     t = {}
     for name, prm in [("fp64", whmc.cg_params(tol=1e-10)),
                       ("mixed_f32_l12", whmc.cg_params(tol=1e-10, prec=whmc.F32, links=whmc.L12, delta=0.1)),

@@ -30,7 +30,7 @@ template <class Lnk, class S>
 __global__ __launch_bounds__(kBlock) void k_cg1(Geom g, Lnk L, S p, S t, const CGScalars* sc) {
   if (halted(sc)) return;
   using R = typename S::Real;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (i >= g.Vh) return;
   Spinor<R> acc;
   hop_site<0>(g, 0, i, L, p, acc);
@@ -41,7 +41,7 @@ template <class Lnk, class S>
 __global__ __launch_bounds__(kBlock) void k_cg2(Geom g, Lnk L, S t, S p, S u, double k2, CGScalars* sc, Reduce red) {
   if (halted(sc)) return;
   using R = typename S::Real;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   double nrm = 0.0;
   if (i < g.Vh) {
     Spinor<R> acc, pv;
@@ -69,7 +69,7 @@ template <class Lnk, class S>
 __global__ __launch_bounds__(kBlock) void k_cg3(Geom g, Lnk L, S u, S v, const CGScalars* sc) {
   if (halted(sc)) return;
   using R = typename S::Real;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (i >= g.Vh) return;
   Spinor<R> acc;
   hop_site<1>(g, 0, i, L, u, acc);
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_cg4(Geom g, Lnk L, S v, S u, S p, SR
   if (halted(sc)) return;
   using R = typename S::Real;
   using RR = typename SR::Real;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   const double alpha = sc->alpha;
   double nrm = 0.0;
   if (i < g.Vh) {
@@ -275,8 +275,9 @@ static whmc_status enqueue_iters(whmc_ctx* c, const Lnk& L, S p, S t, S u, S v, 
 }
 
 // plain FP64 CG for one right-hand side
+template <class Lnk>
 static whmc_status cg_f64(whmc_ctx* c, double* x, const double* b, double kappa, const whmc_cg_params* prm,
-                          whmc_cg_stats* st) {
+                          whmc_cg_stats* st, Lnk L) {
   Timer tm;
   const size_t hb = (size_t)c->Vh * 192;
   void *r, *p, *t, *u, *v, *te, *to;
@@ -288,7 +289,6 @@ static whmc_status cg_f64(whmc_ctx* c, double* x, const double* b, double kappa,
   WHMC_TRY(workspace(c, "cg_te", hb, &te));
   WHMC_TRY(workspace(c, "cg_to", hb, &to));
   const int Vh = c->Vh;
-  const LinkF64_18 L{c->U18, Vh};
   WHMC_TRY(norm2_f64(c, b, 1, c->red.result + 3));
   double bb;
   WHMC_TRY(read_scalar(c, c->red.result + 3, &bb));
@@ -325,7 +325,7 @@ static whmc_status cg_f64(whmc_ctx* c, double* x, const double* b, double kappa,
     while (true) {
       const int n = std::min(check, prm->maxiter - total - pass_iters);
       if (n <= 0) break;
-      WHMC_TRY((enqueue_iters<LinkF64_18, SpinorF64, SpinorF64, false>(c, L, s64(p, Vh), s64(t, Vh), s64(u, Vh),
+      WHMC_TRY((enqueue_iters<Lnk, SpinorF64, SpinorF64, false>(c, L, s64(p, Vh), s64(t, Vh), s64(u, Vh),
                                                                         s64(v, Vh), s64(r, Vh), s64(x, Vh), kappa, n)));
       WHMC_TRY(read_scalars(c, &hs));
       pass_iters = hs.iter;
@@ -440,19 +440,25 @@ whmc_status cg_solve(whmc_ctx* c, double* x, const double* b, const double* kapp
   whmc_status rc;
   const int Vh = c->Vh;
   if (p->prec == WHMC_F64) {
-    rc = cg_f64(c, x, b, kappas[0], p, s);
+    if (c->stream_links(WHMC_F64, WHMC_L18)) rc = cg_f64(c, x, b, kappas[0], p, s, LinkF64_18T<true>{c->U18, Vh});
+    else rc = cg_f64(c, x, b, kappas[0], p, s, LinkF64_18T<false>{c->U18, Vh});
   } else if (p->prec == WHMC_F32) {
+    WHMC_TRY(ensure_links(c, WHMC_F32, p->links));
+    const bool nt = c->stream_links(WHMC_F32, p->links);
     if (p->links == WHMC_L18) {
-      WHMC_TRY(ensure_links(c, WHMC_F32, WHMC_L18));
-      rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF32_18{c->U32_18, Vh}, WHMC_F32, s32, s32, WHMC_F32);
+      if (nt) rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF32_18T<true>{c->U32_18, Vh}, WHMC_F32, s32, s32, WHMC_F32);
+      else rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF32_18T<false>{c->U32_18, Vh}, WHMC_F32, s32, s32, WHMC_F32);
     } else {
-      WHMC_TRY(ensure_links(c, WHMC_F32, WHMC_L12));
-      rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF32_12{c->U32_12, Vh}, WHMC_F32, s32, s32, WHMC_F32);
+      if (nt) rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF32_12T<true>{c->U32_12, Vh}, WHMC_F32, s32, s32, WHMC_F32);
+      else rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF32_12T<false>{c->U32_12, Vh}, WHMC_F32, s32, s32, WHMC_F32);
     }
   } else {
     WHMC_CHECK(p->links == WHMC_L12, WHMC_EUNSUP, "FP16 bulk requires 12-real links");
     WHMC_TRY(ensure_links(c, WHMC_F16, WHMC_L12));
-    rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF16_12{c->U16_12, Vh}, WHMC_F16, s16, s32, WHMC_F32);
+    if (c->stream_links(WHMC_F16, WHMC_L12))
+      rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF16_12T<true>{c->U16_12, Vh}, WHMC_F16, s16, s32, WHMC_F32);
+    else
+      rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF16_12T<false>{c->U16_12, Vh}, WHMC_F16, s16, s32, WHMC_F32);
   }
   if (rc != WHMC_OK) return rc;
   if (!s->converged) {

@@ -31,11 +31,13 @@ whmc_status workspace(whmc_ctx* c, const std::string& name, size_t bytes, void**
 }
 
 // ------------------------------------------------------------------ hop kernels
-template <int DAG, bool XPAY, bool NORM, class Lnk, class SIn, class SX, class SOut>
+// out = a x + b H_{par,1-par}^{(dag)} in; NTS: non-temporal output store (apply_H on large lattices,
+// where the result is not read back by the next kernel); NORM: FP64 |out|^2 reduction.
+template <int DAG, bool XPAY, bool NORM, bool NTS, class Lnk, class SIn, class SX, class SOut>
 __global__ __launch_bounds__(kBlock) void k_hop(Geom g, int par, Lnk L, SIn in, SX x, SOut out, double a,
                                                 double b, Reduce red, double* norm_out) {
   using R = typename SOut::Real;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   double nrm = 0.0;
   if (i < g.Vh) {
     Spinor<R> acc;
@@ -50,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void k_hop(Geom g, int par, Lnk L, SIn in, 
     } else {
       scale(acc, b);
     }
-    out.store(i, acc);
+    out.template store<NTS>(i, acc);
     if (NORM) nrm = norm2(acc);
   }
   if (NORM) grid_sum<kBlock>(nrm, red, norm_out);
@@ -58,17 +60,18 @@ __global__ __launch_bounds__(kBlock) void k_hop(Geom g, int par, Lnk L, SIn in, 
 
 template <class Lnk, class S>
 static whmc_status launch_hop(whmc_ctx* c, const Lnk& L, int par, int dag, S in, S x, S out, bool xpay, double a,
-                              double b, double* norm_out) {
+                              double b, double* norm_out, bool nts) {
   dim3 grid(c->num_blocks()), block(kBlock);
-#define WHMC_L(D, XP, N) hipLaunchKernelGGL((k_hop<D, XP, N, Lnk, S, S, S>), grid, block, 0, c->stream, c->g, par, L, \
-                                            in, x, out, a, b, c->red, norm_out)
+#define WHMC_L(D, XP, N, NS) hipLaunchKernelGGL((k_hop<D, XP, N, NS, Lnk, S, S, S>), grid, block, 0, c->stream, c->g, \
+                                                par, L, in, x, out, a, b, c->red, norm_out)
   const bool norm = norm_out != nullptr;
-  if (dag) {
-    if (xpay) { if (norm) WHMC_L(1, true, true); else WHMC_L(1, true, false); }
-    else      { if (norm) WHMC_L(1, false, true); else WHMC_L(1, false, false); }
+  if (xpay) {
+    if (dag) { if (norm) WHMC_L(1, true, true, false); else WHMC_L(1, true, false, false); }
+    else     { if (norm) WHMC_L(0, true, true, false); else WHMC_L(0, true, false, false); }
   } else {
-    if (xpay) { if (norm) WHMC_L(0, true, true); else WHMC_L(0, true, false); }
-    else      { if (norm) WHMC_L(0, false, true); else WHMC_L(0, false, false); }
+    WHMC_CHECK(!norm, WHMC_EARG, "hop: norm only with the xpay form");
+    if (dag) { if (nts) WHMC_L(1, false, false, true); else WHMC_L(1, false, false, false); }
+    else     { if (nts) WHMC_L(0, false, false, true); else WHMC_L(0, false, false, false); }
   }
 #undef WHMC_L
   WHMC_HIP(hipGetLastError());
@@ -81,27 +84,35 @@ static SpinorF16 sp16(const void* p, int Vh) {
   return SpinorF16{(uint4*)p, p ? (float*)((uint4*)p + (size_t)3 * Vh) : nullptr, Vh};
 }
 
-whmc_status hop(whmc_ctx* c, int prec, int links, int par, int dag, void* out, const void* in, const void* x,
-                double a, double b, double* norm_out) {
-  WHMC_TRY(ensure_links(c, prec, links));
+template <bool NT>
+static whmc_status hop_nt(whmc_ctx* c, int prec, int links, int par, int dag, void* out, const void* in,
+                          const void* x, double a, double b, double* norm_out, bool nts) {
   const bool xpay = x != nullptr;
   const int Vh = c->Vh;
   if (prec == WHMC_F64) {
     if (links == WHMC_L18)
-      return launch_hop(c, LinkF64_18{c->U18, Vh}, par, dag, sp64(in, Vh), sp64(x, Vh), sp64(out, Vh), xpay, a, b,
-                        norm_out);
-    return launch_hop(c, LinkF64_12{c->U12, Vh}, par, dag, sp64(in, Vh), sp64(x, Vh), sp64(out, Vh), xpay, a, b,
-                      norm_out);
+      return launch_hop(c, LinkF64_18T<NT>{c->U18, Vh}, par, dag, sp64(in, Vh), sp64(x, Vh), sp64(out, Vh), xpay, a,
+                        b, norm_out, nts);
+    return launch_hop(c, LinkF64_12T<NT>{c->U12, Vh}, par, dag, sp64(in, Vh), sp64(x, Vh), sp64(out, Vh), xpay, a, b,
+                      norm_out, nts);
   }
   if (prec == WHMC_F32) {
     if (links == WHMC_L18)
-      return launch_hop(c, LinkF32_18{c->U32_18, Vh}, par, dag, sp32(in, Vh), sp32(x, Vh), sp32(out, Vh), xpay, a, b,
-                        norm_out);
-    return launch_hop(c, LinkF32_12{c->U32_12, Vh}, par, dag, sp32(in, Vh), sp32(x, Vh), sp32(out, Vh), xpay, a, b,
-                      norm_out);
+      return launch_hop(c, LinkF32_18T<NT>{c->U32_18, Vh}, par, dag, sp32(in, Vh), sp32(x, Vh), sp32(out, Vh), xpay,
+                        a, b, norm_out, nts);
+    return launch_hop(c, LinkF32_12T<NT>{c->U32_12, Vh}, par, dag, sp32(in, Vh), sp32(x, Vh), sp32(out, Vh), xpay, a,
+                      b, norm_out, nts);
   }
-  return launch_hop(c, LinkF16_12{c->U16_12, Vh}, par, dag, sp16(in, Vh), sp16(x, Vh), sp16(out, Vh), xpay, a, b,
-                    norm_out);
+  return launch_hop(c, LinkF16_12T<NT>{c->U16_12, Vh}, par, dag, sp16(in, Vh), sp16(x, Vh), sp16(out, Vh), xpay, a,
+                    b, norm_out, nts);
+}
+
+whmc_status hop(whmc_ctx* c, int prec, int links, int par, int dag, void* out, const void* in, const void* x,
+                double a, double b, double* norm_out, bool nt_store) {
+  WHMC_TRY(ensure_links(c, prec, links));
+  const bool nt = c->stream_links(prec, links);
+  if (nt) return hop_nt<true>(c, prec, links, par, dag, out, in, x, a, b, norm_out, nt_store && nt);
+  return hop_nt<false>(c, prec, links, par, dag, out, in, x, a, b, norm_out, false);
 }
 
 // ------------------------------------------------------------------ gauge field storage
@@ -553,12 +564,12 @@ whmc_status whmc_apply_H(whmc_ctx* c, void* out, const void* in, int out_parity,
   WHMC_CHECK(prec >= 0 && prec <= 2, WHMC_EARG, "whmc_apply_H: bad precision");
   WHMC_CHECK(links == WHMC_L12 || links == WHMC_L18, WHMC_EARG, "whmc_apply_H: links must be 12 or 18");
   const int dag = dagger ? 1 : 0;
-  if (out_parity >= 0) return hop(c, prec, links, out_parity, dag, out, in, nullptr, 0.0, 1.0, nullptr);
+  if (out_parity >= 0) return hop(c, prec, links, out_parity, dag, out, in, nullptr, 0.0, 1.0, nullptr, true);
   const size_t hb = half_bytes(prec, c->Vh);
   const char* ic = (const char*)in;
   char* oc = (char*)out;
-  WHMC_TRY(hop(c, prec, links, 0, dag, oc, ic + hb, nullptr, 0.0, 1.0, nullptr));
-  return hop(c, prec, links, 1, dag, oc + hb, ic, nullptr, 0.0, 1.0, nullptr);
+  WHMC_TRY(hop(c, prec, links, 0, dag, oc, ic + hb, nullptr, 0.0, 1.0, nullptr, true));
+  return hop(c, prec, links, 1, dag, oc + hb, ic, nullptr, 0.0, 1.0, nullptr, true);
 }
 
 whmc_status whmc_apply_Moo(whmc_ctx* c, double* out, const double* in, double kappa, int dagger) {

@@ -144,6 +144,52 @@ WHMC_DEV int neighbour(const Geom& g, const Coords& c, bool& wrap_t) {
   }
 }
 
+// ------------------------------------------------------------------ cache-policy helpers
+// NT = non-temporal: data streamed once (links of a large lattice, outputs that are not read back
+// soon) is marked so that it does not evict reusable neighbour spinors from L2 / Infinity Cache.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+
+template <bool NT> WHMC_DEV double2 ldg(const double2* p) {
+  if (NT) { d2v v = __builtin_nontemporal_load((const d2v*)p); return make_double2(v.x, v.y); }
+  return *p;
+}
+template <bool NT> WHMC_DEV float4 ldg(const float4* p) {
+  if (NT) { f4v v = __builtin_nontemporal_load((const f4v*)p); return make_float4(v.x, v.y, v.z, v.w); }
+  return *p;
+}
+template <bool NT> WHMC_DEV float2 ldg(const float2* p) {
+  if (NT) { f2v v = __builtin_nontemporal_load((const f2v*)p); return make_float2(v.x, v.y); }
+  return *p;
+}
+template <bool NT> WHMC_DEV uint2 ldg(const uint2* p) {
+  if (NT) { u2v v = __builtin_nontemporal_load((const u2v*)p); return make_uint2(v.x, v.y); }
+  return *p;
+}
+template <bool NT> WHMC_DEV void stg(double2* p, double2 v) {
+  if (NT) __builtin_nontemporal_store(d2v{v.x, v.y}, (d2v*)p);
+  else *p = v;
+}
+template <bool NT> WHMC_DEV void stg(float4* p, float4 v) {
+  if (NT) __builtin_nontemporal_store(f4v{v.x, v.y, v.z, v.w}, (f4v*)p);
+  else *p = v;
+}
+template <bool NT> WHMC_DEV void stg(uint4* p, uint4 v) {
+  if (NT) __builtin_nontemporal_store(u4v{v.x, v.y, v.z, v.w}, (u4v*)p);
+  else *p = v;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Renumber them so
+// that XCD k works on the k-th contiguous eighth of the sites: neighbours in y, z (and x) then
+// sit in the same L2.  Bijective on [0, nb) for any nb.
+WHMC_DEV int xcd_remap(int B, int nb) {
+  const int k = B & 7, m = B >> 3, q = nb >> 3, r = nb & 7;
+  return k * q + (k < r ? k : r) + m;
+}
+
 // ------------------------------------------------------------------ spinor storage
 struct SpinorF64 {
   using Real = double;
@@ -156,9 +202,11 @@ struct SpinorF64 {
       s.c[k / 3][k % 3] = {v.x, v.y};
     }
   }
+  template <bool NT = false>
   WHMC_DEV void store(int i, const Spinor<double>& s) const {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) p[(size_t)k * stride + i] = make_double2(s.c[k / 3][k % 3].re, s.c[k / 3][k % 3].im);
+    for (int k = 0; k < 12; ++k)
+      stg<NT>(p + (size_t)k * stride + i, make_double2(s.c[k / 3][k % 3].re, s.c[k / 3][k % 3].im));
   }
 };
 
@@ -174,11 +222,12 @@ struct SpinorF32 {
       s.c[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v.z, v.w};
     }
   }
+  template <bool NT = false>
   WHMC_DEV void store(int i, const Spinor<float>& s) const {
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       cplx<float> a = s.c[(2 * k) / 3][(2 * k) % 3], b = s.c[(2 * k + 1) / 3][(2 * k + 1) % 3];
-      p[(size_t)k * stride + i] = make_float4(a.re, a.im, b.re, b.im);
+      stg<NT>(p + (size_t)k * stride + i, make_float4(a.re, a.im, b.re, b.im));
     }
   }
 };
@@ -204,6 +253,7 @@ struct SpinorF16 {
       }
     }
   }
+  template <bool NT = false>
   WHMC_DEV void store(int i, const Spinor<float>& s) const {
     float m = 0.f;
 #pragma unroll
@@ -221,14 +271,15 @@ struct SpinorF16 {
         w[j] = (unsigned int)f2h(inv * s.c[comp / 3][comp % 3].re) |
                ((unsigned int)f2h(inv * s.c[comp / 3][comp % 3].im) << 16);
       }
-      p[(size_t)k * stride + i] = make_uint4(w[0], w[1], w[2], w[3]);
+      stg<NT>(p + (size_t)k * stride + i, make_uint4(w[0], w[1], w[2], w[3]));
     }
   }
 };
 
 // ------------------------------------------------------------------ link storage
 // every link type: load(par, mu, i) -> U_{x,mu} for the site x of parity `par`, cb index i.
-struct LinkF64_18 {
+template <bool NT = false>
+struct LinkF64_18T {
   using Real = double;
   const double2* p;
   int Vh;
@@ -236,13 +287,14 @@ struct LinkF64_18 {
     const double2* q = p + ((size_t)(par * 4 + mu) * 9) * Vh + i;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      double2 v = q[(size_t)k * Vh];
+      double2 v = ldg<NT>(q + (size_t)k * Vh);
       U.e[k / 3][k % 3] = {v.x, v.y};
     }
   }
 };
 
-struct LinkF64_12 {
+template <bool NT = false>
+struct LinkF64_12T {
   using Real = double;
   const double2* p;
   int Vh;
@@ -250,14 +302,15 @@ struct LinkF64_12 {
     const double2* q = p + ((size_t)(par * 4 + mu) * 6) * Vh + i;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      double2 v = q[(size_t)k * Vh];
+      double2 v = ldg<NT>(q + (size_t)k * Vh);
       U.e[k / 3][k % 3] = {v.x, v.y};
     }
     reconstruct_row2(U);
   }
 };
 
-struct LinkF32_12 {
+template <bool NT = false>
+struct LinkF32_12T {
   using Real = float;
   const float4* p;
   int Vh;
@@ -265,7 +318,7 @@ struct LinkF32_12 {
     const float4* q = p + ((size_t)(par * 4 + mu) * 3) * Vh + i;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      float4 v = q[(size_t)k * Vh];
+      float4 v = ldg<NT>(q + (size_t)k * Vh);
       U.e[(2 * k) / 3][(2 * k) % 3] = {v.x, v.y};
       U.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v.z, v.w};
     }
@@ -273,7 +326,8 @@ struct LinkF32_12 {
   }
 };
 
-struct LinkF32_18 {
+template <bool NT = false>
+struct LinkF32_18T {
   using Real = float;
   const float2* p;
   int Vh;
@@ -281,13 +335,14 @@ struct LinkF32_18 {
     const float2* q = p + ((size_t)(par * 4 + mu) * 9) * Vh + i;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      float2 v = q[(size_t)k * Vh];
+      float2 v = ldg<NT>(q + (size_t)k * Vh);
       U.e[k / 3][k % 3] = {v.x, v.y};
     }
   }
 };
 
-struct LinkF16_12 {
+template <bool NT = false>
+struct LinkF16_12T {
   using Real = float;
   const uint2* p;
   int Vh;
@@ -295,13 +350,19 @@ struct LinkF16_12 {
     const uint2* q = p + ((size_t)(par * 4 + mu) * 3) * Vh + i;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      uint2 v = q[(size_t)k * Vh];
+      uint2 v = ldg<NT>(q + (size_t)k * Vh);
       U.e[(2 * k) / 3][(2 * k) % 3] = {h2f((unsigned short)(v.x & 0xffffu)), h2f((unsigned short)(v.x >> 16))};
       U.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {h2f((unsigned short)(v.y & 0xffffu)), h2f((unsigned short)(v.y >> 16))};
     }
     reconstruct_row2(U);
   }
 };
+
+using LinkF64_18 = LinkF64_18T<false>;
+using LinkF64_12 = LinkF64_12T<false>;
+using LinkF32_18 = LinkF32_18T<false>;
+using LinkF32_12 = LinkF32_12T<false>;
+using LinkF16_12 = LinkF16_12T<false>;
 
 // ------------------------------------------------------------------ reductions
 // wavefront (64 lanes) then workgroup sum; result valid in thread 0.

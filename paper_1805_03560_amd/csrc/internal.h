@@ -38,7 +38,7 @@ void set_error(const std::string& msg);
     if (s_ != WHMC_OK) return s_;   \
   } while (0)
 
-constexpr int kBlock = 256;
+constexpr int kBlock = 128;   // threads per workgroup of the stencil and reduction kernels
 
 // per-solve scalar state that lives on the device so that iterations can be enqueued without a
 // host round trip; `done` / `pause` make the remaining queued kernels exit at once.
@@ -81,6 +81,15 @@ struct whmc_ctx {
   whmc::CGScalars* scal = nullptr;   // kMaxRhs entries
   whmc::CGScalars* scal_host = nullptr;  // pinned mirror
   double* host_pinned = nullptr;     // small pinned buffer for scalar read-back
+  // cache policy: stream (non-temporal) link loads when the link array of a format is larger
+  // than stream_threshold bytes; -1 = never, 0 = always.  Set by the heuristic in whmc_create or
+  // by whmc_autotune.
+  long long stream_threshold = 128LL << 20;
+  bool stream_links(int prec, int links) const {
+    if (stream_threshold < 0) return false;
+    const long long per = prec == 0 ? (links == 18 ? 144 : 96) : (prec == 1 ? (links == 18 ? 72 : 48) : 24);
+    return (long long)8 * Vh * per > stream_threshold;
+  }
   int num_blocks() const { return (Vh + whmc::kBlock - 1) / whmc::kBlock; }
 };
 
@@ -97,7 +106,7 @@ whmc_status gauge_changed(whmc_ctx* c);   // invalidate derived copies after the
 // out = a * x + b * H_{par,1-par}^{(dag)} in   (x may be null: then out = b * H in)
 // if norm_out != null the FP64 sum |out|^2 is written there (device pointer).
 whmc_status hop(whmc_ctx* c, int prec, int links, int par, int dag, void* out, const void* in, const void* x,
-                double a, double b, double* norm_out);
+                double a, double b, double* norm_out, bool nt_store = false);
 
 // ---- FP64 BLAS on half fields (core.hip); n = number of half fields
 whmc_status axpby_f64(whmc_ctx* c, double* y, double a, const double* x, double b, int nhalf);  // y = a x + b y
