@@ -194,12 +194,83 @@ def extras(ctx, whmc, torch, np, stream, Vh):
         cgr[name]["speedup_vs_fp64"] = round(t["fp64"] / t[name], 3)
     out["cg_32x64_kappa0.1575"] = cgr
 
+    out["multi_rhs_24x48"] = multi_rhs(whmc, torch, stream)
+
     # kappa^4-filtered pseudo-fermion force (n_t = 15), FP64 solves to 1e-10
     phi = b
     ms = time_events(lambda: ctx.force(phi, 2, 15, 29, KAPPA, 5.6, solver=whmc.cg_params(tol=1e-10)), stream, torch)
     out["force_kappa4_nt15_ms"] = round(ms, 1)
     log(f"[bench] filtered force (kappa^4, n_t=15): {ms:.1f} ms")
     return out
+
+
+def multi_rhs(whmc, torch, stream):
+    """24^3 x 48, smooth links (seed 4000): batched hop per rhs and masked multi-RHS CG for 4, 8, 12
+    Gaussian sources (seeds 4100 + r) with mass-preconditioning shifts kappa' in
+    {0.150, 0.153, 0.156, 0.1575}, against the same systems solved one after the other in FP64."""
+    from paper_1805_03560_amd import synth
+    dims = (48, 24, 24, 24)
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    Vh = V // 2
+    U = synth.smooth_links(dims, 4000, threads=min(16, os.cpu_count() or 1))
+    ctx = whmc.Context(dims, device=0)
+    ctx.load_gauge(torch.from_numpy(U).to(ctx.device), unitarity_tol=1e-11)
+    del U
+    kp = [0.150, 0.153, 0.156, 0.1575]
+    res = {}
+    for nrhs in (4, 8, 12):
+        import numpy as np
+        bs = np.stack([synth.gaussian_spinor(Vh, 4100 + r) for r in range(nrhs)])
+        b = ctx.pack_spinor(torch.from_numpy(bs).to(ctx.device), 0)
+        kappas = [kp[r % 4] for r in range(nrhs)]
+        row = {}
+        # batched hop, FP64 18-real (autotuned register block) vs nrhs single hops
+        nb, _ = ctx.autotune(whmc.F64, whmc.L18, nrhs)
+        o = ctx.half_spinor(whmc.F64, nrhs)
+        ms = time_events(lambda: ctx.apply_H_multi(b, 0, nrhs, out=o, rhs_block=nb), stream, torch, reps=10)
+        bytes_launch = Vh * (1152 + 384 * nrhs)
+        row["hop_f64_rhs_block"] = nb
+        row["hop_f64_us_per_rhs"] = round(ms * 1e3 / nrhs, 2)
+        row["hop_f64_GBps"] = round(bytes_launch / (ms * 1e-3) / 1e9, 1)
+        nb32, _ = ctx.autotune(whmc.F32, whmc.L12, nrhs)
+        b32 = ctx.convert_spinor(b, whmc.F64, whmc.F32, nrhs)
+        o32 = ctx.half_spinor(whmc.F32, nrhs)
+        ms32 = time_events(lambda: ctx.apply_H_multi(b32, 0, nrhs, prec=whmc.F32, links=whmc.L12, out=o32,
+                                                     rhs_block=nb32), stream, torch, reps=10)
+        row["hop_f32_l12_rhs_block"] = nb32
+        row["hop_f32_l12_us_per_rhs"] = round(ms32 * 1e3 / nrhs, 2)
+        row["hop_f32_l12_GBps"] = round(Vh * (576 + 192 * nrhs) / (ms32 * 1e-3) / 1e9, 1)
+        # CG to 1e-10: sequential FP64, masked multi-RHS FP64, masked multi-RHS mixed FP32-12
+        def seq():
+            for r in range(nrhs):
+                ctx.cg_solve(b[r * 24 * Vh:(r + 1) * 24 * Vh], [kappas[r]], whmc.cg_params(tol=1e-10))
+        seq()
+        t_seq = time_events(seq, stream, torch)
+        ref, _ = ctx.cg_solve(b, kappas, whmc.cg_params(tol=1e-12))
+        ref = ref.clone()
+        for name, prm in [("multi_fp64", whmc.cg_params(tol=1e-10)),
+                          ("multi_mixed_f32_l12", whmc.cg_params(tol=1e-10, prec=whmc.F32, links=whmc.L12, delta=0.1)),
+                          ("multi_mixed_f16_l12", whmc.cg_params(tol=1e-10, prec=whmc.F16, links=whmc.L12, delta=0.1))]:
+            ctx.cg_solve(b, kappas, prm)
+            holder = {}
+
+            def run():
+                holder["x"], holder["st"] = ctx.cg_solve(b, kappas, prm)
+            t = time_events(run, stream, torch)
+            st = holder["st"]
+            err = max(float(torch.linalg.vector_norm(holder["x"][r * 24 * Vh:(r + 1) * 24 * Vh] -
+                                                     ref[r * 24 * Vh:(r + 1) * 24 * Vh]) /
+                            torch.linalg.vector_norm(ref[r * 24 * Vh:(r + 1) * 24 * Vh])) for r in range(nrhs))
+            row[name] = {"ms": round(t, 2), "speedup_vs_sequential_fp64": round(t_seq / t, 3),
+                         "iters": [s["iters"] for s in st], "max_true_residual": max(s["true_residual"] for s in st),
+                         "max_rel_err_vs_fp64_1e-12": err}
+        row["sequential_fp64_ms"] = round(t_seq, 2)
+        res[f"nrhs{nrhs}"] = row
+        log(f"[bench] multi-RHS {nrhs}: hop {row['hop_f64_us_per_rhs']} us/rhs (nb {nb}), seq {t_seq:.1f} ms, "
+            f"multi fp64 {row['multi_fp64']['ms']} ms, mixed f32 {row['multi_mixed_f32_l12']['ms']} ms, "
+            f"mixed f16 {row['multi_mixed_f16_l12']['ms']} ms")
+    ctx.close()
+    return res
 
 
 def cpu_baseline():

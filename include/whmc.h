@@ -107,9 +107,21 @@ whmc_status whmc_unpack_algebra(whmc_ctx* ctx, double* dst, const double* src);
  * F32 supports L18 and L12; F16 supports L12).  in and out must not overlap. */
 whmc_status whmc_apply_H(whmc_ctx* ctx, void* out, const void* in, int out_parity, int dagger, int prec, int links);
 
+/* Multi right-hand-side form of the even/odd hop: out_r = H_{p,1-p} in_r for r < nrhs (nrhs
+ * consecutive half fields in and out, 1 <= nrhs <= 16).  Each link is loaded once per block of
+ * rhs_block right-hand sides (1..4; 0 = the autotuned block).  Formats: FP64 with 18-real links,
+ * FP32 and FP16 with 12-real links. */
+whmc_status whmc_apply_H_multi(whmc_ctx* ctx, void* out, const void* in, int out_parity, int dagger, int prec,
+                               int links, int nrhs, int rhs_block);
+
+/* Autotuner: time the multi-RHS hop for every register block 1..min(4, nrhs) at this lattice
+ * size, precision and link format, remember the fastest in the context and return it (and its
+ * time per launch in microseconds if us != NULL).  Later calls with the same key return the
+ * stored choice without timing. */
+whmc_status whmc_autotune(whmc_ctx* ctx, int prec, int links, int nrhs, int* rhs_block, double* us);
+
 /* out = M_oo in = in - kappa^2 H_oe H_eo in (dagger = 0) or M_oo^dag in (dagger = 1), FP64,
- * odd-site half fields (Sec. 2.2).  Uses `tmp` (one even half field, FP64) as scratch if given,
- * else context scratch. */
+ * odd-site half fields (Sec. 2.2).  Uses context scratch for the even-site intermediate. */
 whmc_status whmc_apply_Moo(whmc_ctx* ctx, double* out, const double* in, double kappa, int dagger);
 
 /* out_r = M_oo(kappa_r)^dag M_oo(kappa_r) in_r for r < nrhs, FP64, odd-site half fields. */

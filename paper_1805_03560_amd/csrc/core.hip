@@ -437,7 +437,7 @@ whmc_status whmc_create(whmc_ctx** out, const int dims[4], int device, void* str
   c->stream = (hipStream_t)stream;
   const size_t nlinks = (size_t)8 * c->Vh;
   hipError_t e = hipMalloc(&c->U18, nlinks * 9 * sizeof(double2));
-  const int maxb = ((c->Vh + kBlock - 1) / kBlock) * kMaxRhs + 1024 * kMaxRhs;
+  const int maxb = ((c->Vh + kBlock - 1) / kBlock) * (kMaxRhs + 4) + 1024 * kMaxRhs;
   if (e == hipSuccess) e = hipMalloc(&c->red.partials, (size_t)maxb * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&c->red.counter, 64 * sizeof(unsigned));
   if (e == hipSuccess) e = hipMalloc(&c->red.result, 64 * sizeof(double));

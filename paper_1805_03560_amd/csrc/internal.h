@@ -77,6 +77,7 @@ struct whmc_ctx {
   bool derived_valid[4] = {false, false, false, false};  // U12, U32_18, U32_12, U16_12
   // scratch
   std::map<std::string, std::pair<void*, size_t>> ws;
+  std::map<std::string, std::pair<int, double>> tuned;   // autotuned multi-RHS register blocks
   whmc::Reduce red{};
   whmc::CGScalars* scal = nullptr;   // kMaxRhs entries
   whmc::CGScalars* scal_host = nullptr;  // pinned mirror
@@ -128,6 +129,10 @@ whmc_status apply_K_f64(whmc_ctx* c, double* out, const double* in, double kappa
 // ---- solvers (cg.hip)
 whmc_status cg_solve(whmc_ctx* c, double* x, const double* b, const double* kappas, int nrhs,
                      const whmc_cg_params* p, whmc_cg_stats* st);
+
+// ---- multi-RHS (multi.hip)
+whmc_status mhop(whmc_ctx* c, int prec, int links, int par, int dag, int nrhs, int nb, void* out, const void* in);
+whmc_status autotune_rhs_block(whmc_ctx* c, int prec, int links, int nrhs, int* best_nb, double* best_us);
 
 // ---- gauge and force kernels (gauge.hip)
 whmc_status plaquette_sum(whmc_ctx* c, double* host_out);

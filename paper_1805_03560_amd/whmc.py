@@ -85,6 +85,10 @@ _SIGS = {
     "whmc_unpack_algebra": ([_P, _P, _P], ctypes.c_int),
     "whmc_apply_H": ([_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "whmc_apply_Moo": ([_P, _P, _P, ctypes.c_double, ctypes.c_int], ctypes.c_int),
+    "whmc_apply_H_multi": ([_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                            ctypes.c_int], ctypes.c_int),
+    "whmc_autotune": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                       ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "whmc_apply_MdagM": ([_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int], ctypes.c_int),
     "whmc_cg_solve": ([_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.POINTER(CGParams),
                        ctypes.POINTER(CGStats)], ctypes.c_int),
@@ -239,6 +243,18 @@ class Context:
             out = self.half_spinor(prec, 2 if out_parity < 0 else 1)
         _check(lib().whmc_apply_H(self._h, _ptr(out), _ptr(inp), out_parity, int(dagger), prec, links))
         return out
+
+    def apply_H_multi(self, inp, out_parity, nrhs, dagger=False, prec=F64, links=L18, rhs_block=0, out=None):
+        if out is None:
+            out = self.half_spinor(prec, nrhs)
+        _check(lib().whmc_apply_H_multi(self._h, _ptr(out), _ptr(inp), out_parity, int(dagger), prec, links, nrhs,
+                                        rhs_block))
+        return out
+
+    def autotune(self, prec, links, nrhs):
+        nb, us = ctypes.c_int(), ctypes.c_double()
+        _check(lib().whmc_autotune(self._h, prec, links, nrhs, ctypes.byref(nb), ctypes.byref(us)))
+        return nb.value, us.value
 
     def apply_Moo(self, inp, kappa, dagger=False, out=None):
         out = self.half_spinor() if out is None else out

@@ -1,0 +1,75 @@
+"""GPU parity of the multi right-hand-side hop and the masked multi-RHS CG (FP64 and mixed)
+against the oracle, with per-rhs kappa shifts so that the right-hand sides converge unevenly."""
+import numpy as np
+import pytest
+
+from oracle import dirac
+from oracle.lattice import Lattice
+from oracle.solve import cg
+from paper_1805_03560_amd import synth, whmc
+
+from gpu_util import make_ctx, pack_half, rel_err, unpack_half
+
+pytestmark = pytest.mark.gpu
+
+KAPPAS = [0.150, 0.153, 0.156, 0.1575]
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 5])
+@pytest.mark.parametrize("nb", [1, 2, 3, 4])
+def test_multi_hop_fp64_parity(nrhs, nb):
+    dims = (4, 4, 6, 6)
+    lat = Lattice(dims)
+    U = synth.haar_links(dims, 5000)
+    xs = np.stack([synth.gaussian_spinor(lat.Vh, 5001 + r) for r in range(nrhs)])
+    ctx = make_ctx(dims, U)
+    for par, dag in [(0, 0), (1, 1)]:
+        out = ctx.apply_H_multi(pack_half(ctx, xs), par, nrhs, dagger=dag, rhs_block=nb)
+        got = unpack_half(ctx, out, nrhs).reshape(nrhs, lat.Vh, 4, 3)
+        for r in range(nrhs):
+            assert rel_err(got[r], dirac.apply_Hblock(lat, U, xs[r], par, dagger=bool(dag))) < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [(whmc.F32, 2e-6), (whmc.F16, 4e-3)])
+def test_multi_hop_low_precision(prec, tol):
+    dims = (4, 4, 4, 8)
+    lat = Lattice(dims)
+    U = synth.smooth_links(dims, 5010)
+    nrhs = 4
+    xs = np.stack([synth.gaussian_spinor(lat.Vh, 5011 + r) for r in range(nrhs)])
+    ctx = make_ctx(dims, U)
+    xin = ctx.convert_spinor(pack_half(ctx, xs), whmc.F64, prec, nrhs)
+    for nb in (1, 2, 4):
+        out = ctx.apply_H_multi(xin, 1, nrhs, prec=prec, links=whmc.L12, rhs_block=nb)
+        got = unpack_half(ctx, ctx.convert_spinor(out, prec, whmc.F64, nrhs), nrhs).reshape(nrhs, lat.Vh, 4, 3)
+        for r in range(nrhs):
+            assert rel_err(got[r], dirac.apply_Hblock(lat, U, xs[r], 1)) < tol
+
+
+def test_autotuner_returns_a_valid_block():
+    dims = (8, 8, 8, 8)
+    ctx = make_ctx(dims, synth.smooth_links(dims, 5020))
+    nb, us = ctx.autotune(whmc.F64, whmc.L18, 8)
+    assert 1 <= nb <= 4 and us > 0
+    assert ctx.autotune(whmc.F64, whmc.L18, 8)[0] == nb     # remembered
+
+
+@pytest.mark.parametrize("prec,nrhs,nb", [(whmc.F64, 4, 0), (whmc.F64, 5, 2), (whmc.F32, 4, 0), (whmc.F16, 6, 3)])
+def test_masked_multi_rhs_cg(prec, nrhs, nb):
+    dims = (4, 4, 4, 8)
+    lat = Lattice(dims)
+    U = synth.smooth_links(dims, 5030)
+    kappas = [KAPPAS[r % 4] for r in range(nrhs)]
+    bs = np.stack([synth.gaussian_spinor(lat.Vh, 4000 + r) for r in range(nrhs)])
+    ctx = make_ctx(dims, U)
+    prm = whmc.cg_params(tol=1e-10, prec=prec, links=whmc.L18 if prec == whmc.F64 else whmc.L12, delta=0.1,
+                         rhs_block=nb)
+    x, st = ctx.cg_solve(pack_half(ctx, bs), kappas, prm)
+    got = unpack_half(ctx, x, nrhs).reshape(nrhs, lat.Vh, 4, 3)
+    iters = [s["iters"] for s in st]
+    for r, k in enumerate(kappas):
+        ref, _, _ = cg(lambda v: dirac.apply_MooDagMoo(lat, U, v, k), bs[r], tol=1e-14)
+        assert st[r]["converged"] and st[r]["true_residual"] <= 1e-10
+        assert rel_err(got[r], ref) < 1e-8
+    # lighter quarks (larger kappa) need more iterations: the rhs converged at different times
+    assert len(set(iters)) > 1, iters
