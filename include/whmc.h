@@ -197,6 +197,18 @@ whmc_status whmc_plaquette(whmc_ctx* ctx, double* plaq);
 whmc_status whmc_force(whmc_ctx* ctx, double* F, const double* phi, const whmc_filter* f, double kappa,
                        double beta, const whmc_cg_params* solver, int flags);
 
+/* Molecular-dynamics primitives (Sec. 1, with the step conventions of this library):
+ * T step  U_{x,mu} <- exp(eps Pi_{x,mu}) U_{x,mu}  (exact SU(3) exponential, FP64 master copy;
+ *         lower-precision copies are re-derived on next use), and
+ * P step  Pi <- Pi - eps F  (algebra layout). */
+whmc_status whmc_update_links(whmc_ctx* ctx, const double* pi, double eps);
+whmc_status whmc_update_momenta(whmc_ctx* ctx, double* pi, const double* F, double eps);
+
+/* Chain rule through the exponential chart U(omega) = exp(omega) U0: given the force F at U(omega)
+ * (algebra layout), out = sum_k (-ad_omega)^k F / (k+1)!, the gradient of S(exp(omega) U0) with
+ * respect to the coordinates of omega (equal to F at omega = 0).  out must not alias the inputs. */
+whmc_status whmc_dexp_transpose(whmc_ctx* ctx, double* out, const double* omega, const double* F);
+
 /* ------------------------------------------------------------------ HMC (Sec. 1, 4.1)
  * One trajectory: phi = M~ eta, H0, molecular dynamics with Sexton-Weingarten levels (gauge on
  * level 0 with m0 steps per coarse step, pseudo-fermion on level 1 with m steps over tau),

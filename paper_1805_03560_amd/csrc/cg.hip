@@ -1,7 +1,8 @@
 // Conjugate gradient on A = M_oo^dag M_oo (Sec. 1 names CG for the pseudo-fermion systems; Sec.
 // 2.2 the even/odd matrix), FP64 and mixed precision.
 //
-// One iteration is five kernels; the scalars (alpha, beta, |r|^2) never leave the device:
+// One iteration is five stencil / vector kernels, plus two single-block kernels that finish the
+// two reductions (see block_partial); the scalars (alpha, beta, |r|^2) never leave the device:
 //   1  t = H_eo p
 //   2  u = p - kappa^2 H_oe t,                (p, A p) = |u|^2      -> alpha = |r|^2 / |u|^2
 //   3  v = (H^dag)_eo u
@@ -54,15 +55,21 @@ __global__ __launch_bounds__(kBlock) void k_cg2(Geom g, Lnk L, S t, S p, S u, do
     u.store(i, acc);
     nrm = norm2(acc);
   }
-  grid_sum_then<kBlock>(nrm, red, [=](double pAp) {
-    sc->pAp = pAp;
-    if (pAp > 0.0 && pAp < INFINITY) {
-      sc->alpha = sc->rr / pAp;
-    } else {
-      sc->alpha = 0.0;
-      sc->done = 1;   // breakdown: p = 0 or non-finite
-    }
-  });
+  block_partial<kBlock>(nrm, red.partials, blockIdx.x);
+}
+
+// pass 2 of kernel 2: (p, A p) -> alpha
+__global__ __launch_bounds__(256) void k_cg2_fin(CGScalars* sc, const double* partials, int nb) {
+  if (halted(sc)) return;
+  const double pAp = sum_partials<256>(partials, nb);
+  if (threadIdx.x != 0) return;
+  sc->pAp = pAp;
+  if (pAp > 0.0 && pAp < INFINITY) {
+    sc->alpha = sc->rr / pAp;
+  } else {
+    sc->alpha = 0.0;
+    sc->done = 1;   // breakdown: p = 0 or non-finite
+  }
 }
 
 template <class Lnk, class S>
@@ -107,23 +114,30 @@ __global__ __launch_bounds__(kBlock) void k_cg4(Geom g, Lnk L, S v, S u, S p, SR
     x.store(i, xv);
     nrm = norm2(rv);
   }
-  grid_sum_then<kBlock>(nrm, red, [=](double rr_new) {
-    const double rr_old = sc->rr;
-    sc->beta = rr_new / rr_old;
-    sc->rr_old = rr_old;
-    sc->rr = rr_new;
-    sc->iter += 1;
-    if (!(rr_new < INFINITY)) {
-      sc->done = 1;
-      return;
-    }
-    if (MIXED) {
-      sc->rmax2 = fmax(sc->rmax2, rr_new);
-      if (rr_new <= sc->stop_rr || rr_new < sc->delta2 * sc->rmax2) sc->pause = 1;
-    } else {
-      if (rr_new <= sc->stop_rr) sc->done = 1;
-    }
-  });
+  block_partial<kBlock>(nrm, red.partials, blockIdx.x);
+}
+
+// pass 2 of kernel 4: new |r|^2 -> beta, stop / reliable-update tests
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_cg4_fin(CGScalars* sc, const double* partials, int nb) {
+  if (halted(sc)) return;
+  const double rr_new = sum_partials<256>(partials, nb);
+  if (threadIdx.x != 0) return;
+  const double rr_old = sc->rr;
+  sc->beta = rr_new / rr_old;
+  sc->rr_old = rr_old;
+  sc->rr = rr_new;
+  sc->iter += 1;
+  if (!(rr_new < INFINITY)) {
+    sc->done = 1;
+    return;
+  }
+  if (MIXED) {
+    sc->rmax2 = fmax(sc->rmax2, rr_new);
+    if (rr_new <= sc->stop_rr || rr_new < sc->delta2 * sc->rmax2) sc->pause = 1;
+  } else {
+    if (rr_new <= sc->stop_rr) sc->done = 1;
+  }
 }
 
 template <class S, class SR>
@@ -226,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_dot_rp(int Vh, S p, SR r, Reduce red
       for (int c = 0; c < 3; ++c)
         s += (double)pv.c[a][c].re * (double)rv.c[a][c].re + (double)pv.c[a][c].im * (double)rv.c[a][c].im;
   }
-  grid_sum<kBlock>(s, red, out);
+  block_partial<kBlock>(s, red.partials, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ host drivers
@@ -265,9 +279,11 @@ static whmc_status enqueue_iters(whmc_ctx* c, const Lnk& L, S p, S t, S u, S v, 
   for (int it = 0; it < n; ++it) {
     hipLaunchKernelGGL((k_cg1<Lnk, S>), grid, block, 0, c->stream, c->g, L, p, t, c->scal);
     hipLaunchKernelGGL((k_cg2<Lnk, S>), grid, block, 0, c->stream, c->g, L, t, p, u, k2, c->scal, c->red);
+    hipLaunchKernelGGL(k_cg2_fin, dim3(1), dim3(256), 0, c->stream, c->scal, c->red.partials, (int)grid.x);
     hipLaunchKernelGGL((k_cg3<Lnk, S>), grid, block, 0, c->stream, c->g, L, u, v, c->scal);
     hipLaunchKernelGGL((k_cg4<Lnk, S, SR, MIXED>), grid, block, 0, c->stream, c->g, L, v, u, p, r, x, k2, c->scal,
                        c->red);
+    hipLaunchKernelGGL(k_cg4_fin<MIXED>, dim3(1), dim3(256), 0, c->stream, c->scal, c->red.partials, (int)grid.x);
     hipLaunchKernelGGL((k_cg5<S, SR>), grid, block, 0, c->stream, c->Vh, p, r, c->scal);
   }
   WHMC_HIP(hipGetLastError());
@@ -412,6 +428,7 @@ static whmc_status cg_mixed(whmc_ctx* c, double* x, const double* b, double kapp
     hipLaunchKernelGGL(k_cg_resume, dim3(1), dim3(64), 0, c->stream, c->scal, c->red.result + 5);
     hipLaunchKernelGGL((k_dot_rp<S, SR>), grid, block, 0, c->stream, Vh, mk(p, Vh), mkr(rs, Vh), c->red,
                        c->red.result + 6);
+    WHMC_TRY(finish_sum(c, (int)grid.x, c->red.result + 6));
     hipLaunchKernelGGL((k_rel_p<S, SR>), grid, block, 0, c->stream, Vh, mk(p, Vh), mkr(rs, Vh), c->red.result + 6,
                        c->scal);
     WHMC_HIP(hipGetLastError());

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kBlock) void k_hop(Geom g, int par, Lnk L, SIn in, 
     out.template store<NTS>(i, acc);
     if (NORM) nrm = norm2(acc);
   }
-  if (NORM) grid_sum<kBlock>(nrm, red, norm_out);
+  if (NORM) block_partial<kBlock>(nrm, red.partials, blockIdx.x);
 }
 
 template <class Lnk, class S>
@@ -75,6 +75,7 @@ static whmc_status launch_hop(whmc_ctx* c, const Lnk& L, int par, int dag, S in,
   }
 #undef WHMC_L
   WHMC_HIP(hipGetLastError());
+  if (norm) return finish_sum(c, (int)grid.x, norm_out);
   return WHMC_OK;
 }
 
@@ -332,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_dot(long long n, const double2* x, c
     double2 a = x[i], b = y[i];
     s += a.x * b.x + a.y * b.y;
   }
-  grid_sum<kBlock>(s, red, out);
+  block_partial<kBlock>(s, red.partials, blockIdx.x);
 }
 
 static dim3 flat_grid(long long n) { return dim3((unsigned)((n + 255) / 256)); }
@@ -365,12 +366,19 @@ static int reduce_blocks(whmc_ctx* c, long long n) {
   long long b = (n + kBlock - 1) / kBlock;
   return (int)(b < 1024 ? b : 1024);
 }
-whmc_status dot_re_f64(whmc_ctx* c, const double* x, const double* y, int nhalf, double* dev_out) {
-  const long long n = 12LL * c->Vh * nhalf;
-  hipLaunchKernelGGL(k_dot, dim3(reduce_blocks(c, n)), dim3(kBlock), 0, c->stream, n, (const double2*)x,
-                     (const double2*)y, c->red, dev_out);
+whmc_status finish_sum(whmc_ctx* c, int nparts, double* dev_out) {
+  hipLaunchKernelGGL(k_finish_sum<256>, dim3(1), dim3(256), 0, c->stream, c->red.partials, nparts, dev_out);
   WHMC_HIP(hipGetLastError());
   return WHMC_OK;
+}
+
+whmc_status dot_re_f64(whmc_ctx* c, const double* x, const double* y, int nhalf, double* dev_out) {
+  const long long n = 12LL * c->Vh * nhalf;
+  const int nb = reduce_blocks(c, n);
+  hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kBlock), 0, c->stream, n, (const double2*)x, (const double2*)y, c->red,
+                     dev_out);
+  WHMC_HIP(hipGetLastError());
+  return finish_sum(c, nb, dev_out);
 }
 whmc_status norm2_f64(whmc_ctx* c, const double* x, int nhalf, double* dev_out) {
   return dot_re_f64(c, x, x, nhalf, dev_out);

@@ -383,44 +383,40 @@ WHMC_DEV double block_sum(double v, double* lds) {
 
 struct Reduce {
   double* partials;    // per-block partial sums
-  unsigned* counter;   // last-block-done counter (reset by the last block)
+  unsigned* counter;   // unused by the two-pass scheme (kept for the ABI-internal layout)
   double* result;      // final sums
 };
 
-// ------------------------------------------------------------------ grid-wide FP64 sums
-// Each block writes its partial sum; the last block to finish (atomic counter) adds the partials
-// in a fixed order, so the result is deterministic, and resets the counter.
-// Grid-wide FP64 sum: each block writes its partial; the last block to finish (atomic counter)
-// adds the partials in a fixed order -- so the result is deterministic -- resets the counter and
-// hands the total to fin(total) in its thread 0.  Every thread of the grid must call this.
-template <int BLOCK, class Fin>
-WHMC_DEV void grid_sum_then(double v, const Reduce& red, Fin fin) {
+// Two-pass deterministic reductions.  Pass 1: each block reduces its values and writes one
+// partial per value with a plain store -- no fence or atomic, which on gfx950 would force an
+// L2 write-back per block (the 8 XCD L2s are not coherent within a kernel).  Pass 2 (a separate,
+// tiny kernel, so the kernel boundary makes the partials visible) adds the partials of each value
+// in a fixed order.  Every thread of the pass-1 grid must call block_partial.
+template <int BLOCK>
+WHMC_DEV void block_partial(double v, double* partials, int slot) {
   __shared__ double lds[BLOCK / 64];
-  __shared__ int last;
-  double s = block_sum<BLOCK>(v, lds);
-  if (threadIdx.x == 0) {
-    red.partials[blockIdx.x] = s;
-    __threadfence();
-    unsigned prev = atomicAdd(red.counter, 1u);
-    last = (prev == gridDim.x - 1);
-  }
   __syncthreads();
-  if (last) {
-    __threadfence();
-    double t = 0.0;
-    for (int k = threadIdx.x; k < (int)gridDim.x; k += BLOCK) t += red.partials[k];
-    __syncthreads();
-    t = block_sum<BLOCK>(t, lds);
-    if (threadIdx.x == 0) {
-      *red.counter = 0u;
-      fin(t);
-    }
-  }
+  const double s = block_sum<BLOCK>(v, lds);
+  if (threadIdx.x == 0) partials[slot] = s;
 }
 
 template <int BLOCK>
-WHMC_DEV void grid_sum(double v, const Reduce& red, double* out) {
-  grid_sum_then<BLOCK>(v, red, [=](double t) { *out = t; });
+__global__ __launch_bounds__(BLOCK) void k_finish_sum(const double* partials, int n, double* out);
+
+// pass 2 helper: sum of p[0..n) by one block of BLOCK threads in a fixed order; valid in thread 0
+template <int BLOCK>
+WHMC_DEV double sum_partials(const double* p, int n) {
+  __shared__ double lds[BLOCK / 64];
+  double t = 0.0;
+  for (int k = threadIdx.x; k < n; k += BLOCK) t += p[k];
+  __syncthreads();
+  return block_sum<BLOCK>(t, lds);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_finish_sum(const double* partials, int n, double* out) {
+  const double t = sum_partials<BLOCK>(partials, n);
+  if (threadIdx.x == 0) *out = t;
 }
 
 }  // namespace whmc

@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_plaquette(Geom g, const double2* __r
           for (int l = 0; l < 3; ++l) s += t2.e[k][l].re * d.e[k][l].re + t2.e[k][l].im * d.e[k][l].im;
       }
   }
-  grid_sum<kBlock>(s, red, out);
+  block_partial<kBlock>(s, red.partials, blockIdx.x);
 }
 
 whmc_status plaquette_sum(whmc_ctx* c, double* host_out) {
@@ -163,6 +163,7 @@ whmc_status plaquette_sum(whmc_ctx* c, double* host_out) {
   const int nb = (2 * c->Vh + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_plaquette, dim3(nb), dim3(kBlock), 0, c->stream, c->g, c->U18, c->red, c->red.result);
   WHMC_HIP(hipGetLastError());
+  WHMC_TRY(finish_sum(c, nb, c->red.result));
   return read_scalar(c, c->red.result, host_out);
 }
 
@@ -192,10 +193,8 @@ __global__ __launch_bounds__(kBlock) void k_gauge_force(Geom g, const double2* _
     load_link(U18, g.Vh, shift(g, c, mu, 1, nu, -1), nu, a);
     load_link(U18, g.Vh, shift(g, c, nu, -1), mu, b);
     load_link(U18, g.Vh, shift(g, c, nu, -1), nu, d);
-    matmul_dn(a, b, t1);     // a^dag b^dag = (b a)^dag -> compute as a^dag * b^dag
-    // matmul_dn gives a^dag b; we need a^dag b^dag: use t1 = a^dag, then * b^dag
     {
-      SU3<double> ad;
+      SU3<double> ad;   // a^dag, then t1 = a^dag b^dag
       for (int p = 0; p < 3; ++p)
         for (int q = 0; q < 3; ++q) ad.e[p][q] = conj(a.e[q][p]);
       matmul_nd(ad, b, t1);
@@ -363,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_sumsq(long long n, const double* x, 
   double s = 0.0;
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
     s += x[i] * x[i];
-  grid_sum<kBlock>(s, red, out);
+  block_partial<kBlock>(s, red.partials, blockIdx.x);
 }
 
 whmc_status algebra_norm2(whmc_ctx* c, const double* pi, double* host_out) {
@@ -372,6 +371,7 @@ whmc_status algebra_norm2(whmc_ctx* c, const double* pi, double* host_out) {
   if (nb > 1024) nb = 1024;
   hipLaunchKernelGGL(k_sumsq, dim3((unsigned)nb), dim3(kBlock), 0, c->stream, n, pi, c->red, c->red.result + 1);
   WHMC_HIP(hipGetLastError());
+  WHMC_TRY(finish_sum(c, (int)nb, c->red.result + 1));
   return read_scalar(c, c->red.result + 1, host_out);
 }
 
@@ -403,7 +403,61 @@ whmc_status pack_algebra(whmc_ctx* c, double* dst, const double* src, int unpack
   return WHMC_OK;
 }
 
+// Transpose of the differential of the exponential map, for S(exp(omega) U0): with
+// d/dt exp(omega + t eta) = [sum_k ad_omega^k(eta) / (k+1)!] exp(omega) and ad_omega antisymmetric
+// for (A,B) = -2 Re Tr(AB), the gradient in eta is  sum_k (-ad_omega)^k F / (k+1)!.
+__global__ __launch_bounds__(kBlock) void k_dexp_t(int Vh, const double* omega, const double* F, double* out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int pm = blockIdx.y;
+  if (i >= Vh) return;
+  double a[8], f[8];
+  for (int k = 0; k < 8; ++k) {
+    a[k] = omega[((size_t)pm * 8 + k) * Vh + i];
+    f[k] = F[((size_t)pm * 8 + k) * Vh + i];
+  }
+  SU3<double> W, T, R, A, B;
+  from_coords(a, W);
+  from_coords(f, T);
+  R = T;
+  for (int k = 1; k <= 30; ++k) {
+    matmul(W, T, A);
+    matmul(T, W, B);
+    const double s = -1.0 / (k + 1);
+    double mx = 0.0;
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q) {
+        T.e[p][q] = s * (A.e[p][q] - B.e[p][q]);
+        R.e[p][q] = R.e[p][q] + T.e[p][q];
+        mx = fmax(mx, fmax(fabs(T.e[p][q].re), fabs(T.e[p][q].im)));
+      }
+    if (mx < 1e-18) break;
+  }
+  double g[8];
+  ta_coords(R, g);
+  // ta_coords returns Im Tr(lambda_a R) = coordinates of the (already antihermitian) R
+  for (int k = 0; k < 8; ++k) out[((size_t)pm * 8 + k) * Vh + i] = g[k];
+}
+
 }  // namespace whmc
+
+extern "C" whmc_status whmc_update_links(whmc_ctx* c, const double* pi, double eps) {
+  WHMC_CHECK(c && pi, WHMC_EARG, "whmc_update_links: null argument");
+  return whmc::link_update(c, pi, eps);
+}
+
+extern "C" whmc_status whmc_update_momenta(whmc_ctx* c, double* pi, const double* F, double eps) {
+  WHMC_CHECK(c && pi && F && pi != F, WHMC_EARG, "whmc_update_momenta: bad argument");
+  return whmc::mom_update(c, pi, F, eps);
+}
+
+extern "C" whmc_status whmc_dexp_transpose(whmc_ctx* c, double* out, const double* omega, const double* F) {
+  WHMC_CHECK(c && out && omega && F, WHMC_EARG, "whmc_dexp_transpose: null argument");
+  WHMC_CHECK(out != omega && out != F, WHMC_EARG, "whmc_dexp_transpose: out must not alias the inputs");
+  hipLaunchKernelGGL(whmc::k_dexp_t, dim3(c->num_blocks(), 8), dim3(whmc::kBlock), 0, c->stream, c->Vh, omega, F,
+                     out);
+  WHMC_HIP(hipGetLastError());
+  return WHMC_OK;
+}
 
 extern "C" whmc_status whmc_plaquette(whmc_ctx* c, double* plaq) {
   WHMC_CHECK(c && plaq, WHMC_EARG, "whmc_plaquette: null argument");

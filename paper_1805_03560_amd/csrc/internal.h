@@ -116,6 +116,7 @@ whmc_status gamma5_f64(whmc_ctx* c, double* y, const double* x, int nhalf);
 whmc_status norm2_f64(whmc_ctx* c, const double* x, int nhalf, double* dev_out);      // async, device result
 whmc_status dot_re_f64(whmc_ctx* c, const double* x, const double* y, int nhalf, double* dev_out);
 whmc_status read_scalar(whmc_ctx* c, const double* dev, double* host);                // synchronises
+whmc_status finish_sum(whmc_ctx* c, int nparts, double* dev_out);   // pass 2 over red.partials[0..nparts)
 whmc_status convert_spinor(whmc_ctx* c, void* dst, int dst_prec, const void* src, int src_prec, int nhalf);
 whmc_status zero_bytes(whmc_ctx* c, void* p, size_t bytes);   // fill kernel (graph-safe)
 

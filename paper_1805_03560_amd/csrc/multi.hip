@@ -32,39 +32,18 @@ struct K2 {
   double v[kMaxRhs];
 };
 
-// ------------------------------------------------------------------ multi-value grid reduction
-// Per rhs j of this grid.y slice: block partial -> partials[(slice*NB + j) * nb + block]; the last
-// block of the slice adds them in a fixed order and calls fin(j, total).
-template <int BLOCK, int NB, class Fin>
-WHMC_DEV void grid_sum_multi(const double* v, const Reduce& red, int slice, Fin fin) {
-  __shared__ double lds[BLOCK / 64];
-  __shared__ int last;
-  double s[NB];
-#pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    __syncthreads();
-    s[j] = block_sum<BLOCK>(v[j], lds);
-  }
+// ------------------------------------------------------------------ per-rhs partial sums
+// pass 1: rhs r of this block's slice writes its block partial to partials[r * nb + block];
+// pass 2 (k_m*_fin, one block per rhs) adds the nb partials of rhs r in a fixed order.
+template <int BLOCK, int NB>
+WHMC_DEV void block_partials_multi(const double* v, double* partials, int r0, int nrhs) {
   const int nb = gridDim.x;
-  if (threadIdx.x == 0) {
 #pragma unroll
-    for (int j = 0; j < NB; ++j) red.partials[(size_t)(slice * NB + j) * nb + blockIdx.x] = s[j];
-    __threadfence();
-    const unsigned prev = atomicAdd(red.counter + slice, 1u);
-    last = (prev == (unsigned)nb - 1);
-  }
-  __syncthreads();
-  if (last) {
-    __threadfence();
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      double t = 0.0;
-      for (int k = threadIdx.x; k < nb; k += BLOCK) t += red.partials[(size_t)(slice * NB + j) * nb + k];
-      __syncthreads();
-      t = block_sum<BLOCK>(t, lds);
-      if (threadIdx.x == 0) fin(j, t);
-    }
-    if (threadIdx.x == 0) red.counter[slice] = 0u;
+  for (int k = 0; k < NB; ++k) {
+    __shared__ double lds[BLOCK / 64];
+    __syncthreads();
+    const double s = block_sum<BLOCK>(v[k], lds);
+    if (threadIdx.x == 0 && r0 + k < nrhs) partials[(size_t)(r0 + k) * nb + blockIdx.x] = s;
   }
 }
 
@@ -198,17 +177,21 @@ __global__ __launch_bounds__(kBlock) void k_mcg2(Geom g, int nrhs, Lnk L, S t0, 
       nrm[k] = norm2(acc[k]);
     }
   }
-  grid_sum_multi<kBlock, NB>(nrm, red, blockIdx.y, [=](int k, double pAp) {
-    const int r = r0 + k;
-    if (r >= nrhs || !act[k]) return;
-    sc[r].pAp = pAp;
-    if (pAp > 0.0 && pAp < INFINITY) {
-      sc[r].alpha = sc[r].rr / pAp;
-    } else {
-      sc[r].alpha = 0.0;
-      sc[r].done = 1;
-    }
-  });
+  block_partials_multi<kBlock, NB>(nrm, red.partials, r0, nrhs);
+}
+
+__global__ __launch_bounds__(256) void k_mcg2_fin(CGScalars* sc, int nrhs, const double* partials, int nb) {
+  const int r = blockIdx.x;
+  if (!rhs_live(sc, r, nrhs)) return;
+  const double pAp = sum_partials<256>(partials + (size_t)r * nb, nb);
+  if (threadIdx.x != 0) return;
+  sc[r].pAp = pAp;
+  if (pAp > 0.0 && pAp < INFINITY) {
+    sc[r].alpha = sc[r].rr / pAp;
+  } else {
+    sc[r].alpha = 0.0;
+    sc[r].done = 1;
+  }
 }
 
 template <int NB, class Lnk, class S>
@@ -278,26 +261,31 @@ __global__ __launch_bounds__(kBlock) void k_mcg4(Geom g, int nrhs, Lnk L, S v0, 
       nrm[k] = norm2(rv);
     }
   }
-  grid_sum_multi<kBlock, NB>(nrm, red, blockIdx.y, [=](int k, double rr_new) {
-    const int r = r0 + k;
-    if (r >= nrhs || !act[k]) return;
-    CGScalars& q = sc[r];
-    const double rr_old = q.rr;
-    q.beta = rr_new / rr_old;
-    q.rr_old = rr_old;
-    q.rr = rr_new;
-    q.iter += 1;
-    if (!(rr_new < INFINITY)) {
-      q.done = 1;
-      return;
-    }
-    if (MIXED) {
-      q.rmax2 = fmax(q.rmax2, rr_new);
-      if (rr_new <= q.stop_rr || rr_new < q.delta2 * q.rmax2) q.pause = 1;
-    } else {
-      if (rr_new <= q.stop_rr) q.done = 1;
-    }
-  });
+  block_partials_multi<kBlock, NB>(nrm, red.partials, r0, nrhs);
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_mcg4_fin(CGScalars* sc, int nrhs, const double* partials, int nb) {
+  const int r = blockIdx.x;
+  if (!rhs_live(sc, r, nrhs)) return;
+  const double rr_new = sum_partials<256>(partials + (size_t)r * nb, nb);
+  if (threadIdx.x != 0) return;
+  CGScalars& q = sc[r];
+  const double rr_old = q.rr;
+  q.beta = rr_new / rr_old;
+  q.rr_old = rr_old;
+  q.rr = rr_new;
+  q.iter += 1;
+  if (!(rr_new < INFINITY)) {
+    q.done = 1;
+    return;
+  }
+  if (MIXED) {
+    q.rmax2 = fmax(q.rmax2, rr_new);
+    if (rr_new <= q.stop_rr || rr_new < q.delta2 * q.rmax2) q.pause = 1;
+  } else {
+    if (rr_new <= q.stop_rr) q.done = 1;
+  }
 }
 
 template <class S, class SR>
@@ -451,6 +439,16 @@ __global__ void k_mresume(CGScalars* sc, int r, const double* rr, int converged)
   sc[r].pause = 0;
 }
 
+// FP64 restart of rhs r from its true residual: |r|^2 from the device, threshold tol^2 |b|^2
+__global__ void k_mrestart(CGScalars* sc, int r, const double* rr, double stop_rr) {
+  if (threadIdx.x != 0) return;
+  sc[r].rr = *rr;
+  sc[r].stop_rr = stop_rr;
+  sc[r].rmax2 = *rr;
+  sc[r].done = (*rr <= stop_rr);
+  sc[r].pause = 0;
+}
+
 template <class SR>
 __global__ void k_maccum_x(int Vh, double2* x, SR xs) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -483,7 +481,7 @@ __global__ __launch_bounds__(kBlock) void k_mdot_rp(int Vh, S p, SR r, Reduce re
       for (int cc = 0; cc < 3; ++cc)
         s += (double)pv.c[a][cc].re * (double)rv.c[a][cc].re + (double)pv.c[a][cc].im * (double)rv.c[a][cc].im;
   }
-  grid_sum<kBlock>(s, red, out);
+  block_partial<kBlock>(s, red.partials, blockIdx.x);
 }
 
 template <class S, class SR>
@@ -512,9 +510,12 @@ static void enqueue_multi(whmc_ctx* c, int nrhs, const Lnk& L, S p, S t, S u, S 
   for (int it = 0; it < n; ++it) {
     hipLaunchKernelGGL((k_mcg1<NB, Lnk, S>), grid, block, 0, c->stream, c->g, nrhs, L, p, t, c->scal);
     hipLaunchKernelGGL((k_mcg2<NB, Lnk, S>), grid, block, 0, c->stream, c->g, nrhs, L, t, p, u, k2, c->scal, c->red);
+    hipLaunchKernelGGL(k_mcg2_fin, dim3(nrhs), dim3(256), 0, c->stream, c->scal, nrhs, c->red.partials, (int)grid.x);
     hipLaunchKernelGGL((k_mcg3<NB, Lnk, S>), grid, block, 0, c->stream, c->g, nrhs, L, u, v, c->scal);
     hipLaunchKernelGGL((k_mcg4<NB, Lnk, S, SR, MIXED>), grid, block, 0, c->stream, c->g, nrhs, L, v, u, p, r, x, k2,
                        c->scal, c->red);
+    hipLaunchKernelGGL(k_mcg4_fin<MIXED>, dim3(nrhs), dim3(256), 0, c->stream, c->scal, nrhs, c->red.partials,
+                       (int)grid.x);
     hipLaunchKernelGGL((k_mcg5<S, SR>), grid5, block, 0, c->stream, c->Vh, nrhs, p, r, c->scal);
   }
 }
@@ -601,96 +602,110 @@ whmc_status cg_solve_multi(whmc_ctx* c, double* x, const double* b, const double
   K2 k2{};
   for (int r = 0; r < nrhs; ++r) k2.v[r] = kappas[r] * kappas[r];
   std::vector<int> rel_updates(nrhs, 0), conv(nrhs, 0);
-  std::vector<double> true_rel(nrhs, 0.0);
   const int check = prm->check_every > 0 ? prm->check_every : 8;
-  int max_iter_seen = 0;
   CGScalars* hs = c->scal_host;
-  while (true) {
-    WHMC_TRY(with_format(c, prec, links, [&](auto L, auto mk) {
-      if (mixed)
-        return enqueue_multi_nb<true>(c, nb, nrhs, L, mk(p, Vh), mk(t, Vh), mk(u, Vh), mk(v, Vh), h32(rs, Vh),
-                                      h32(xs, Vh), k2, check);
-      return enqueue_multi_nb<false>(c, nb, nrhs, L, mk(p, Vh), mk(t, Vh), mk(u, Vh), mk(v, Vh), h64(rs, Vh),
-                                     h64(xs, Vh), k2, check);
-    }));
+  std::vector<double> rel_final(nrhs, 0.0);
+  bool all = false;
+  for (int pass = 0; pass < 4 && !all; ++pass) {
+    int max_iter_seen = 0;
+    while (true) {
+      WHMC_TRY(with_format(c, prec, links, [&](auto L, auto mk) {
+        if (mixed)
+          return enqueue_multi_nb<true>(c, nb, nrhs, L, mk(p, Vh), mk(t, Vh), mk(u, Vh), mk(v, Vh), h32(rs, Vh),
+                                        h32(xs, Vh), k2, check);
+        return enqueue_multi_nb<false>(c, nb, nrhs, L, mk(p, Vh), mk(t, Vh), mk(u, Vh), mk(v, Vh), h64(rs, Vh),
+                                       h64(xs, Vh), k2, check);
+      }));
+      WHMC_HIP(hipMemcpyAsync(hs, c->scal, nrhs * sizeof(CGScalars), hipMemcpyDeviceToHost, c->stream));
+      WHMC_HIP(hipStreamSynchronize(c->stream));
+      bool live = false;
+      max_iter_seen = 0;
+      for (int r = 0; r < nrhs; ++r) max_iter_seen = std::max(max_iter_seen, hs[r].iter);
+      for (int r = 0; r < nrhs; ++r) {
+        const CGScalars q = hs[r];
+        if (mixed && q.pause && !q.done) {
+          // reliable update of rhs r in FP64
+          double* xr = x + (size_t)r * 24 * Vh;
+          const double* br = b + (size_t)r * 24 * Vh;
+          char* xsr = (char*)xs + rb * r;
+          char* rsr = (char*)rs + rb * r;
+          char* pr = (char*)p + sb * r;
+          hipLaunchKernelGGL((k_maccum_x<SpinorF32>), dim3((Vh + 255) / 256), dim3(256), 0, c->stream, Vh,
+                             (double2*)xr, h32(xsr, Vh));
+          WHMC_HIP(hipGetLastError());
+          double rel;
+          WHMC_TRY(true_residual_r(c, (double*)r64, xr, br, kappas[r], (double*)te, (double*)to, bb[r], &rel));
+          rel_updates[r] += 1;
+          const int ok = rel <= prm->tol;
+          if (!ok) {
+            WHMC_TRY(convert_spinor(c, rsr, WHMC_F32, r64, WHMC_F64, 1));
+            WHMC_TRY(norm2_f64(c, (double*)r64, 1, c->red.result + 5));
+          }
+          hipLaunchKernelGGL(k_mresume, dim3(1), dim3(64), 0, c->stream, c->scal, r, c->red.result + 5, ok);
+          if (!ok) {
+            const dim3 gr(c->num_blocks());
+            WHMC_TRY(with_format(c, prec, links, [&](auto L, auto mk) {
+              (void)L;
+              hipLaunchKernelGGL((k_mdot_rp<decltype(mk(pr, Vh)), SpinorF32>), gr, dim3(kBlock), 0, c->stream, Vh,
+                                 mk(pr, Vh), h32(rsr, Vh), c->red, c->red.result + 6);
+              if (finish_sum(c, (int)gr.x, c->red.result + 6) != WHMC_OK) return WHMC_EHIP;
+              hipLaunchKernelGGL((k_mrel_p<decltype(mk(pr, Vh)), SpinorF32>), gr, dim3(kBlock), 0, c->stream, Vh,
+                                 mk(pr, Vh), h32(rsr, Vh), c->red.result + 6, c->scal + r);
+              return WHMC_OK;
+            }));
+          }
+          WHMC_HIP(hipGetLastError());
+          conv[r] = ok;
+          if (!ok) live = true;
+        } else if (!q.done) {
+          live = true;
+        }
+      }
+      if (!live || max_iter_seen >= prm->maxiter) break;
+    }
+    // FP64 solutions and their true residuals
     WHMC_HIP(hipMemcpyAsync(hs, c->scal, nrhs * sizeof(CGScalars), hipMemcpyDeviceToHost, c->stream));
     WHMC_HIP(hipStreamSynchronize(c->stream));
-    bool live = false;
-    max_iter_seen = 0;
-    for (int r = 0; r < nrhs; ++r) max_iter_seen = std::max(max_iter_seen, hs[r].iter);
+    all = true;
     for (int r = 0; r < nrhs; ++r) {
-      const CGScalars q = hs[r];
-      if (mixed && q.pause && !q.done) {
-        // reliable update of rhs r in FP64
-        double* xr = x + (size_t)r * 24 * Vh;
-        const double* br = b + (size_t)r * 24 * Vh;
-        char* xsr = (char*)xs + rb * r;
-        char* rsr = (char*)rs + rb * r;
-        char* pr = (char*)p + sb * r;
-        hipLaunchKernelGGL((k_maccum_x<SpinorF32>), dim3((Vh + 255) / 256), dim3(256), 0, c->stream, Vh,
-                           (double2*)xr, h32(xsr, Vh));
-        WHMC_HIP(hipGetLastError());
-        double rel;
+      double* xr = x + (size_t)r * 24 * Vh;
+      const double* br = b + (size_t)r * 24 * Vh;
+      if (mixed) {
+        if (!conv[r]) {
+          hipLaunchKernelGGL((k_maccum_x<SpinorF32>), dim3((Vh + 255) / 256), dim3(256), 0, c->stream, Vh,
+                             (double2*)xr, h32((char*)xs + rb * r, Vh));
+          WHMC_HIP(hipGetLastError());
+        }
+      } else {
+        WHMC_HIP(hipMemcpyAsync(xr, (char*)xs + rb * r, hb, hipMemcpyDeviceToDevice, c->stream));
+      }
+      double rel = 0.0;
+      if (bb[r] != 0.0)
         WHMC_TRY(true_residual_r(c, (double*)r64, xr, br, kappas[r], (double*)te, (double*)to, bb[r], &rel));
-        rel_updates[r] += 1;
-        true_rel[r] = rel;
-        const int ok = rel <= prm->tol;
-        if (!ok) {
-          WHMC_TRY(convert_spinor(c, rsr, WHMC_F32, r64, WHMC_F64, 1));
-          WHMC_TRY(norm2_f64(c, (double*)r64, 1, c->red.result + 5));
-        }
-        hipLaunchKernelGGL(k_mresume, dim3(1), dim3(64), 0, c->stream, c->scal, r, c->red.result + 5, ok);
-        if (!ok) {
-          const dim3 gr(c->num_blocks());
-          WHMC_TRY(with_format(c, prec, links, [&](auto L, auto mk) {
-            (void)L;
-            hipLaunchKernelGGL((k_mdot_rp<decltype(mk(pr, Vh)), SpinorF32>), gr, dim3(kBlock), 0, c->stream, Vh,
-                               mk(pr, Vh), h32(rsr, Vh), c->red, c->red.result + 6);
-            hipLaunchKernelGGL((k_mrel_p<decltype(mk(pr, Vh)), SpinorF32>), gr, dim3(kBlock), 0, c->stream, Vh,
-                               mk(pr, Vh), h32(rsr, Vh), c->red.result + 6, c->scal + r);
-            return WHMC_OK;
-          }));
-        }
-        WHMC_HIP(hipGetLastError());
-        conv[r] = ok;
-        if (!ok) live = true;
-      } else if (!q.done) {
-        live = true;
-      }
-    }
-    if (!live || max_iter_seen >= prm->maxiter) break;
-  }
-  // final: FP64 solutions, true residuals
-  WHMC_HIP(hipMemcpyAsync(hs, c->scal, nrhs * sizeof(CGScalars), hipMemcpyDeviceToHost, c->stream));
-  WHMC_HIP(hipStreamSynchronize(c->stream));
-  bool all = true;
-  for (int r = 0; r < nrhs; ++r) {
-    double* xr = x + (size_t)r * 24 * Vh;
-    if (mixed) {
-      if (!conv[r]) {
-        hipLaunchKernelGGL((k_maccum_x<SpinorF32>), dim3((Vh + 255) / 256), dim3(256), 0, c->stream, Vh,
-                           (double2*)xr, h32((char*)xs + rb * r, Vh));
+      rel_final[r] = rel;
+      const bool ok = rel <= prm->tol;
+      if (!ok && !mixed) {
+        // restart this rhs from its true residual (r64 = b - A x): r = p = r64, x continues
+        WHMC_HIP(hipMemcpyAsync((char*)rs + rb * r, r64, hb, hipMemcpyDeviceToDevice, c->stream));
+        WHMC_HIP(hipMemcpyAsync((char*)p + sb * r, r64, hb, hipMemcpyDeviceToDevice, c->stream));
+        WHMC_TRY(norm2_f64(c, (double*)r64, 1, c->red.result + 5));
+        hipLaunchKernelGGL(k_mrestart, dim3(1), dim3(64), 0, c->stream, c->scal, r, c->red.result + 5,
+                           prm->tol * prm->tol * bb[r]);
         WHMC_HIP(hipGetLastError());
       }
-    } else {
-      WHMC_HIP(hipMemcpyAsync(xr, (char*)xs + rb * r, hb, hipMemcpyDeviceToDevice, c->stream));
+      all = all && ok;
     }
-    double rel;
-    WHMC_TRY(true_residual_r(c, (double*)r64, xr, b + (size_t)r * 24 * Vh, kappas[r], (double*)te, (double*)to, bb[r],
-                             &rel));
-    if (bb[r] == 0.0) rel = 0.0;
-    const int ok = rel <= prm->tol;
-    all = all && ok;
-    if (st) {
-      st[r].iters = hs[r].iter;
-      st[r].reliable_updates = rel_updates[r];
-      st[r].converged = ok;
-      st[r].true_residual = rel;
-    }
+    if (mixed || max_iter_seen >= prm->maxiter) break;
   }
   const double secs = tm.s();
   if (st)
-    for (int r = 0; r < nrhs; ++r) st[r].seconds = secs;
+    for (int r = 0; r < nrhs; ++r) {
+      st[r].iters = hs[r].iter;
+      st[r].reliable_updates = rel_updates[r];
+      st[r].converged = rel_final[r] <= prm->tol;
+      st[r].true_residual = rel_final[r];
+      st[r].seconds = secs;
+    }
   if (!all) {
     set_error("multi-RHS CG: not every right-hand side reached the tolerance");
     return WHMC_ENOCONV;

@@ -101,6 +101,9 @@ _SIGS = {
     "whmc_plaquette": ([_P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "whmc_force": ([_P, _P, _P, ctypes.POINTER(Filter), ctypes.c_double, ctypes.c_double,
                     ctypes.POINTER(CGParams), ctypes.c_int], ctypes.c_int),
+    "whmc_update_links": ([_P, _P, ctypes.c_double], ctypes.c_int),
+    "whmc_update_momenta": ([_P, _P, _P, ctypes.c_double], ctypes.c_int),
+    "whmc_dexp_transpose": ([_P, _P, _P, _P], ctypes.c_int),
     "whmc_hmc_trajectory": ([_P, ctypes.POINTER(HMCParams), _P, _P, ctypes.c_double, ctypes.POINTER(TrajResult)],
                             ctypes.c_int),
     "whmc_md_integrate": ([_P, ctypes.POINTER(HMCParams), _P, _P], ctypes.c_int),
@@ -304,6 +307,18 @@ class Context:
         f = Filter(k, n_t, n_max)
         _check(lib().whmc_force(self._h, _ptr(out), _ptr(phi), ctypes.byref(f), kappa, beta,
                                 ctypes.byref(solver) if solver is not None else None, flags))
+        return out
+
+    def update_links(self, pi, eps):
+        _check(lib().whmc_update_links(self._h, _ptr(pi), float(eps)))
+
+    def update_momenta(self, pi, F, eps):
+        _check(lib().whmc_update_momenta(self._h, _ptr(pi), _ptr(F), float(eps)))
+        return pi
+
+    def dexp_transpose(self, omega, F):
+        out = self.algebra()
+        _check(lib().whmc_dexp_transpose(self._h, _ptr(out), _ptr(omega), _ptr(F)))
         return out
 
     def hmc_trajectory(self, params, pi0, eta, u):
