@@ -178,6 +178,7 @@ def extras(ctx, whmc, torch, np, stream, Vh):
     ref = ref.clone()
     t = {}
     for name, prm in [("fp64", whmc.cg_params(tol=1e-10)),
+                      ("fp64_l12", whmc.cg_params(tol=1e-10, links=whmc.L12)),
                       ("mixed_f32_l12", MIXED_F32(whmc)),
                       ("mixed_f16_l12", MIXED_F16(whmc))]:
         ctx.cg_solve(b, [KAPPA], prm)      # warm-up of this path
@@ -194,11 +195,12 @@ def extras(ctx, whmc, torch, np, stream, Vh):
         cgr[name] = {"ms": round(ms, 2), "iters": s["iters"], "reliable_updates": s["reliable_updates"],
                      "true_residual": s["true_residual"], "rel_err_vs_fp64_solution": err}
         log(f"[bench] CG {name}: {ms:.1f} ms, {s['iters']} iters, res {s['true_residual']:.2e}, err {err:.2e}")
-    for name in ("mixed_f32_l12", "mixed_f16_l12"):
+    for name in ("fp64_l12", "mixed_f32_l12", "mixed_f16_l12"):
         cgr[name]["speedup_vs_fp64"] = round(t["fp64"] / t[name], 3)
     out["cg_32x64_kappa0.1575"] = cgr
 
     out["multi_rhs_24x48"] = multi_rhs(whmc, torch, stream)
+    out["hmc_32x64"] = hmc_section(ctx, whmc, torch, stream, Vh)
 
     # kappa^4-filtered pseudo-fermion force (n_t = 15), FP64 solves to 1e-10
     phi = b
@@ -275,6 +277,73 @@ def multi_rhs(whmc, torch, stream):
             f"mixed f16 {row['multi_mixed_f16_l12']['ms']} ms")
     ctx.close()
     return res
+
+
+def hmc_section(ctx, whmc, torch, stream, Vh):
+    """32^3 x 64 HMC (beta = 5.6, kappa = 0.1575, kappa^4 filter with n_t = 15, n_max = 29, Omelyan
+    lambda = 1/6, gauge on 4 fine steps per coarse step, tau = 1): one trajectory with mixed FP16
+    MD solves, Delta H at m = 10 and 20, reversibility, and a central finite difference of the
+    total action along a random algebra direction against the force."""
+    import math
+    from paper_1805_03560_amd import synth
+    dims = DIMS
+    U0 = ctx.export_gauge()
+    pi0 = ctx.pack_algebra(torch.from_numpy(synth.gaussian_momenta(dims, 3100)).to(ctx.device))
+    eta = ctx.pack_spinor(torch.from_numpy(synth.gaussian_spinor(Vh, 3101)).to(ctx.device), 0)
+    md_mixed = whmc.cg_params(tol=1e-10, prec=whmc.F16, links=whmc.L12, delta=1e-2)
+    fp64_tight = whmc.cg_params(tol=1e-12)
+    mk = lambda m, md: whmc.hmc_params(beta=5.6, kappa=KAPPA, k=2, n_t=15, n_max=29, integrator=whmc.OMELYAN,
+                                       lam=1.0 / 6.0, m=m, m0=4, tau=1.0, md_solver=md, action_solver=fp64_tight)
+    out = {}
+    t0 = time.perf_counter()
+    res = ctx.hmc_trajectory(mk(10, md_mixed), pi0, eta, 0.5)
+    out["trajectory_m10"] = {"seconds": round(time.perf_counter() - t0, 3), "dH": res["dH"],
+                             "accepted": res["accepted"], "plaquette": res["plaquette"],
+                             "cg_iters": res["cg_iters"], "n_solves": res["n_solves"]}
+    log(f"[bench] HMC 32^3x64 trajectory: {out['trajectory_m10']}")
+    ctx.load_gauge(U0, unitarity_tol=0.0)
+    phi = ctx.heatbath_phi(eta, 2, 15, 29, KAPPA)
+    dh = {}
+    for m in (10, 20):
+        ctx.load_gauge(U0, unitarity_tol=0.0)
+        p = mk(m, md_mixed)
+        pi = pi0.clone()
+        H0 = ctx.hamiltonian(p, pi, phi)
+        ctx.md_integrate(p, pi, phi)
+        dh[m] = ctx.hamiltonian(p, pi, phi) - H0
+        if m == 10:
+            ctx.md_integrate(p, -pi, phi)
+            U2 = ctx.export_gauge()
+            d = (U2 - U0).abs()
+            out["reversibility_mixed_1e-10"] = {"max_abs_dU": float(d.max()), "Delta": float((d * d).sum())}
+    out["dH"] = {"m10": dh[10], "m20": dh[20], "ratio": dh[10] / dh[20] if dh[20] != 0 else None}
+    # reversibility with FP64 solves to 1e-12
+    ctx.load_gauge(U0, unitarity_tol=0.0)
+    p = mk(10, fp64_tight)
+    pi = pi0.clone()
+    ctx.md_integrate(p, pi, phi)
+    ctx.md_integrate(p, -pi, phi)
+    d = (ctx.export_gauge() - U0).abs()
+    out["reversibility_fp64_1e-12"] = {"max_abs_dU": float(d.max()), "Delta": float((d * d).sum())}
+    log(f"[bench] HMC dH {out['dH']}, reversibility {out['reversibility_mixed_1e-10']} / {out['reversibility_fp64_1e-12']}")
+    # finite difference of S_G + S~_PF along a random direction vs (omega, F)
+    ctx.load_gauge(U0, unitarity_tol=0.0)
+    tight = whmc.cg_params(tol=1e-14, maxiter=20000)
+    F = ctx.force(phi, 2, 29, 29, KAPPA, 5.6, flags=whmc.FORCE_PF | whmc.FORCE_GAUGE, solver=tight)
+    omega = ctx.pack_algebra(torch.from_numpy(synth.random_algebra(dims, 3102)).to(ctx.device))
+    dd = float(torch.dot(omega, F))
+    def S(e):
+        ctx.load_gauge(U0, unitarity_tol=0.0)
+        ctx.update_links(omega, e)
+        sg, spf = ctx.action(phi, 2, 29, 29, KAPPA, 5.6, solver=tight)
+        return sg + spf
+    eps = 1e-3
+    fd = (8 * (S(eps) - S(-eps)) - (S(2 * eps) - S(-2 * eps))) / (12 * eps)
+    out["force_fd_check"] = {"directional_derivative": dd, "finite_difference": fd,
+                             "rel_err": abs(dd - fd) / abs(fd), "eps": eps, "solver_tol": 1e-14}
+    log(f"[bench] force FD check: {out['force_fd_check']}")
+    ctx.load_gauge(U0, unitarity_tol=0.0)
+    return out
 
 
 def cpu_baseline():

@@ -109,8 +109,8 @@ whmc_status whmc_apply_H(whmc_ctx* ctx, void* out, const void* in, int out_parit
 
 /* Multi right-hand-side form of the even/odd hop: out_r = H_{p,1-p} in_r for r < nrhs (nrhs
  * consecutive half fields in and out, 1 <= nrhs <= 16).  Each link is loaded once per block of
- * rhs_block right-hand sides (1..4; 0 = the autotuned block).  Formats: FP64 with 18-real links,
- * FP32 and FP16 with 12-real links. */
+ * rhs_block right-hand sides (1..4; 0 = the autotuned block).  Formats: FP64 with 18- or 12-real
+ * links, FP32 and FP16 with 12-real links. */
 whmc_status whmc_apply_H_multi(whmc_ctx* ctx, void* out, const void* in, int out_parity, int dagger, int prec,
                                int links, int nrhs, int rhs_block);
 
@@ -130,7 +130,7 @@ whmc_status whmc_apply_MdagM(whmc_ctx* ctx, double* out, const double* in, const
 /* ------------------------------------------------------------------ solver (Sec. 1, 4)
  * Solve M_oo(kappa_r)^dag M_oo(kappa_r) x_r = b_r (odd-site half fields, FP64 whmc layout) by CG
  * from x_r = 0, until the true FP64 residual |b - A x| / |b| <= tol for every r.
- *   prec = WHMC_F64: plain FP64 CG.
+ *   prec = WHMC_F64: plain FP64 CG (links = WHMC_L12 rebuilds the third link row in FP64).
  *   prec = WHMC_F32 / WHMC_F16: mixed precision; the Krylov bulk runs with spinors in that
  *     format and `links`-real links of the same precision, FP64 reliable updates recompute
  *     r = b - A x whenever the iterated residual drops below delta times its maximum since the

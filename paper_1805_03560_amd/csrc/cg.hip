@@ -456,7 +456,12 @@ whmc_status cg_solve(whmc_ctx* c, double* x, const double* b, const double* kapp
   whmc_cg_stats* s = st ? st : &local;
   whmc_status rc;
   const int Vh = c->Vh;
-  if (p->prec == WHMC_F64) {
+  if (p->prec == WHMC_F64 && p->links == WHMC_L12) {
+    // FP64 arithmetic with 12-real links: the third row is rebuilt in FP64, exact to rounding
+    WHMC_TRY(ensure_links(c, WHMC_F64, WHMC_L12));
+    if (c->stream_links(WHMC_F64, WHMC_L12)) rc = cg_f64(c, x, b, kappas[0], p, s, LinkF64_12T<true>{c->U12, Vh});
+    else rc = cg_f64(c, x, b, kappas[0], p, s, LinkF64_12T<false>{c->U12, Vh});
+  } else if (p->prec == WHMC_F64) {
     if (c->stream_links(WHMC_F64, WHMC_L18)) rc = cg_f64(c, x, b, kappas[0], p, s, LinkF64_18T<true>{c->U18, Vh});
     else rc = cg_f64(c, x, b, kappas[0], p, s, LinkF64_18T<false>{c->U18, Vh});
   } else if (p->prec == WHMC_F32) {

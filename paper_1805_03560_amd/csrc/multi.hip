@@ -348,6 +348,10 @@ static whmc_status with_format(whmc_ctx* c, int prec, int links, F&& f) {
     if (nt) return f(LinkF64_18T<true>{c->U18, Vh}, h64);
     return f(LinkF64_18T<false>{c->U18, Vh}, h64);
   }
+  if (prec == WHMC_F64 && links == WHMC_L12) {
+    if (nt) return f(LinkF64_12T<true>{c->U12, Vh}, h64);
+    return f(LinkF64_12T<false>{c->U12, Vh}, h64);
+  }
   if (prec == WHMC_F32 && links == WHMC_L12) {
     if (nt) return f(LinkF32_12T<true>{c->U32_12, Vh}, h32);
     return f(LinkF32_12T<false>{c->U32_12, Vh}, h32);
@@ -356,7 +360,7 @@ static whmc_status with_format(whmc_ctx* c, int prec, int links, F&& f) {
     if (nt) return f(LinkF16_12T<true>{c->U16_12, Vh}, h16);
     return f(LinkF16_12T<false>{c->U16_12, Vh}, h16);
   }
-  set_error("multi-RHS kernels support FP64 with 18-real links and FP32 / FP16 with 12-real links");
+  set_error("multi-RHS kernels support FP64 with 18- or 12-real links and FP32 / FP16 with 12-real links");
   return WHMC_EUNSUP;
 }
 
@@ -549,7 +553,7 @@ whmc_status cg_solve_multi(whmc_ctx* c, double* x, const double* b, const double
   Timer tm;
   const bool mixed = prm->prec != WHMC_F64;
   const int prec = prm->prec;
-  const int links = mixed ? prm->links : WHMC_L18;
+  const int links = prm->links;
   if (mixed && links != WHMC_L12) {
     // no multi-RHS kernels for this format: solve the right-hand sides one after the other
     whmc_cg_params one = *prm;

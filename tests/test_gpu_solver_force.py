@@ -24,9 +24,10 @@ def test_cg_fp64_parity(dims, gen):
     kappa = 0.156
     ref, _, _ = cg(lambda v: dirac.apply_MooDagMoo(lat, U, v, kappa), b, tol=1e-14)
     ctx = make_ctx(dims, U)
-    x, st = ctx.cg_solve(pack_half(ctx, b), [kappa], whmc.cg_params(tol=1e-13, check_every=4))
-    assert st[0]["converged"] and st[0]["true_residual"] <= 1e-13
-    assert rel_err(unpack_half(ctx, x), ref) < 1e-11
+    for links in (whmc.L18, whmc.L12):
+        x, st = ctx.cg_solve(pack_half(ctx, b), [kappa], whmc.cg_params(tol=1e-13, check_every=4, links=links))
+        assert st[0]["converged"] and st[0]["true_residual"] <= 1e-13
+        assert rel_err(unpack_half(ctx, x), ref) < 1e-11
     # at the 1e-10 tolerance of the workloads: error bounded by cond x 1e-10
     x, st = ctx.cg_solve(pack_half(ctx, b), [kappa], whmc.cg_params(tol=1e-10))
     assert st[0]["true_residual"] <= 1e-10
