@@ -14,14 +14,17 @@
  *     T_a = i lambda_a / 2 (Gell-Mann lambda_a), so (Pi,Pi) = -2 sum Tr Pi^2 = sum pi_a^2.
  *
  * Memory.  Every field pointer is DEVICE memory owned by the caller (e.g. a torch tensor on the
- * context's GPU); the library never frees it.  Device layouts ("whmc layout"):
- *   half spinor F64   double2 [12][Vh]        complex component c = 3*spin+colour of site cb
- *   half spinor F32   float4  [6][Vh]         complex components (2k, 2k+1) in float4 k
- *   half spinor F16   uint4   [3][Vh], then float [Vh]  (4 complex as halves per uint4, divided
- *                                             by the per-site scale that follows the halves)
+ * context's GPU); the library never frees it.  Device layouts ("whmc layout"): per-site fields of
+ * K components over the Vh sites of one parity are stored in blocks of 64 sites -- component k of
+ * site cb at element (cb/64)*64*K + k*w + cb%64, w = 64 for full blocks and w = Vh%64 for the last
+ * block -- so a field is exactly K*Vh elements:
+ *   half spinor F64   double2, K = 12         complex component 3*spin+colour
+ *   half spinor F32   float4,  K = 6          complex components (2k, 2k+1) in float4 k
+ *   half spinor F16   uint4,   K = 3, then float [Vh] per-site scales (4 complex as halves per
+ *                                             uint4, divided by the site's scale)
  *   full spinor       two half spinors, even parity first
  *   nrhs spinors      nrhs consecutive fields
- *   algebra field     double [2][4][8][Vh]    [parity][mu][a][cb]  (momenta, forces)
+ *   algebra field     double [2][4][8][Vh]    [parity][mu][a][cb]  (momenta, forces; plain SoA)
  * Canonical layouts (for import/export only):
  *   gauge    complex128 [V][4][3][3]          U_{x,mu}[row][col], x in lex order
  *   spinor   complex128 [V][4][3] (full) or [Vh][4][3] (one parity, cb order)

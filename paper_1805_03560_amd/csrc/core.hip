@@ -108,6 +108,66 @@ static whmc_status hop_nt(whmc_ctx* c, int prec, int links, int par, int dag, vo
                     b, norm_out, nts);
 }
 
+// Full-lattice H in one launch: logical block b applies the parity-(b & 1) block of H to the sites
+// of region b >> 1, so each XCD works on both parities of its contiguous region.
+template <int DAG, bool NTS, class Lnk, class S>
+__global__ __launch_bounds__(kBlock) void k_hop_full(Geom g, Lnk L, S in_e, S in_o, S out_e, S out_o) {
+  using R = typename S::Real;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int par = b & 1;
+  const int i = (b >> 1) * kBlock + threadIdx.x;
+  if (i >= g.Vh) return;
+  Spinor<R> acc;
+  hop_site<DAG>(g, par, i, L, par ? in_e : in_o, acc);
+  (par ? out_o : out_e).template store<NTS>(i, acc);
+}
+
+template <class Lnk, class S>
+static whmc_status launch_full(whmc_ctx* c, const Lnk& L, int dag, S ie, S io, S oe, S oo, bool nts) {
+  dim3 grid(2 * c->num_blocks()), block(kBlock);
+  if (dag) {
+    if (nts) hipLaunchKernelGGL((k_hop_full<1, true, Lnk, S>), grid, block, 0, c->stream, c->g, L, ie, io, oe, oo);
+    else hipLaunchKernelGGL((k_hop_full<1, false, Lnk, S>), grid, block, 0, c->stream, c->g, L, ie, io, oe, oo);
+  } else {
+    if (nts) hipLaunchKernelGGL((k_hop_full<0, true, Lnk, S>), grid, block, 0, c->stream, c->g, L, ie, io, oe, oo);
+    else hipLaunchKernelGGL((k_hop_full<0, false, Lnk, S>), grid, block, 0, c->stream, c->g, L, ie, io, oe, oo);
+  }
+  WHMC_HIP(hipGetLastError());
+  return WHMC_OK;
+}
+
+static size_t half_bytes(int prec, int Vh);
+
+template <bool NT>
+static whmc_status hop_full_nt(whmc_ctx* c, int prec, int links, int dag, void* out, const void* in, bool nts) {
+  const int Vh = c->Vh;
+  const size_t hb = half_bytes(prec, Vh);
+  const char* i0 = (const char*)in;
+  char* o0 = (char*)out;
+  if (prec == WHMC_F64) {
+    auto ie = sp64(i0, Vh), io = sp64(i0 + hb, Vh), oe = sp64(o0, Vh), oo = sp64(o0 + hb, Vh);
+    if (links == WHMC_L18) return launch_full(c, LinkF64_18T<NT>{c->U18, Vh}, dag, ie, io, oe, oo, nts);
+    return launch_full(c, LinkF64_12T<NT>{c->U12, Vh}, dag, ie, io, oe, oo, nts);
+  }
+  if (prec == WHMC_F32) {
+    auto ie = sp32(i0, Vh), io = sp32(i0 + hb, Vh), oe = sp32(o0, Vh), oo = sp32(o0 + hb, Vh);
+    if (links == WHMC_L18) return launch_full(c, LinkF32_18T<NT>{c->U32_18, Vh}, dag, ie, io, oe, oo, nts);
+    return launch_full(c, LinkF32_12T<NT>{c->U32_12, Vh}, dag, ie, io, oe, oo, nts);
+  }
+  auto ie = sp16(i0, Vh), io = sp16(i0 + hb, Vh), oe = sp16(o0, Vh), oo = sp16(o0 + hb, Vh);
+  return launch_full(c, LinkF16_12T<NT>{c->U16_12, Vh}, dag, ie, io, oe, oo, nts);
+}
+
+whmc_status hop_full(whmc_ctx* c, int prec, int links, int dag, void* out, const void* in) {
+  WHMC_TRY(ensure_links(c, prec, links));
+  if (prec == WHMC_F16 && links != WHMC_L12) {
+    set_error("unsupported precision / link format combination");
+    return WHMC_EUNSUP;
+  }
+  if (c->stream_links(prec, links)) return hop_full_nt<true>(c, prec, links, dag, out, in, true);
+  return hop_full_nt<false>(c, prec, links, dag, out, in, false);
+}
+
 whmc_status hop(whmc_ctx* c, int prec, int links, int par, int dag, void* out, const void* in, const void* x,
                 double a, double b, double* norm_out, bool nt_store) {
   WHMC_TRY(ensure_links(c, prec, links));
@@ -132,7 +192,7 @@ __global__ void k_pack_gauge(Geom g, const double2* __restrict__ Ucan, double2* 
   for (int mu = 0; mu < 4; ++mu)
     for (int k = 0; k < 9; ++k) {
       size_t ci = ((size_t)lex * 4 + mu) * 9 + k;
-      size_t si = ((size_t)(par * 4 + mu) * 9 + k) * g.Vh + cb;
+      size_t si = (size_t)(par * 4 + mu) * 9 * g.Vh + aos(k, cb, 9, g.Vh);
       if (unpack) ((double2*)Ucan)[ci] = U18[si];
       else U18[si] = Ucan[ci];
     }
@@ -146,7 +206,7 @@ __global__ void k_unitarity(int n, const double2* __restrict__ U18, int Vh, unsi
     const int pm = idx / Vh, i = idx - pm * Vh;
     SU3<double> U;
     for (int k = 0; k < 9; ++k) {
-      double2 v = U18[((size_t)pm * 9 + k) * Vh + i];
+      double2 v = U18[(size_t)pm * 9 * Vh + aos(k, i, 9, Vh)];
       U.e[k / 3][k % 3] = {v.x, v.y};
     }
     for (int a = 0; a < 3; ++a)
@@ -173,24 +233,24 @@ __global__ void k_derive_links(int n, int Vh, const double2* __restrict__ U18, i
   if (idx >= n) return;
   const int pm = idx / Vh, i = idx - pm * Vh;
   double2 v[9];
-  for (int k = 0; k < 9; ++k) v[k] = U18[((size_t)pm * 9 + k) * Vh + i];
+  for (int k = 0; k < 9; ++k) v[k] = U18[(size_t)pm * 9 * Vh + aos(k, i, 9, Vh)];
   if (fmt == 0) {  // F64-12
     double2* d = (double2*)dst;
-    for (int k = 0; k < 6; ++k) d[((size_t)pm * 6 + k) * Vh + i] = v[k];
+    for (int k = 0; k < 6; ++k) d[(size_t)pm * 6 * Vh + aos(k, i, 6, Vh)] = v[k];
   } else if (fmt == 1) {  // F32-18
     float2* d = (float2*)dst;
-    for (int k = 0; k < 9; ++k) d[((size_t)pm * 9 + k) * Vh + i] = make_float2((float)v[k].x, (float)v[k].y);
+    for (int k = 0; k < 9; ++k) d[(size_t)pm * 9 * Vh + aos(k, i, 9, Vh)] = make_float2((float)v[k].x, (float)v[k].y);
   } else if (fmt == 2) {  // F32-12
     float4* d = (float4*)dst;
     for (int k = 0; k < 3; ++k)
-      d[((size_t)pm * 3 + k) * Vh + i] =
+      d[(size_t)pm * 3 * Vh + aos(k, i, 3, Vh)] =
           make_float4((float)v[2 * k].x, (float)v[2 * k].y, (float)v[2 * k + 1].x, (float)v[2 * k + 1].y);
   } else {  // F16-12
     uint2* d = (uint2*)dst;
     for (int k = 0; k < 3; ++k) {
       unsigned int w0 = (unsigned)f2h((float)v[2 * k].x) | ((unsigned)f2h((float)v[2 * k].y) << 16);
       unsigned int w1 = (unsigned)f2h((float)v[2 * k + 1].x) | ((unsigned)f2h((float)v[2 * k + 1].y) << 16);
-      d[((size_t)pm * 3 + k) * Vh + i] = make_uint2(w0, w1);
+      d[(size_t)pm * 3 * Vh + aos(k, i, 3, Vh)] = make_uint2(w0, w1);
     }
   }
 }
@@ -248,7 +308,7 @@ __global__ void k_pack_spinor(Geom g, double2* dst, const double2* src, int pari
   const size_t field_off = (size_t)f * n_sites * 12;   // same element count in both layouts
   for (int k = 0; k < 12; ++k) {
     size_t ci = field_off + (size_t)s * 12 + k;
-    size_t si = field_off + ((size_t)par * 12 + k) * g.Vh + cb;
+    size_t si = field_off + (size_t)par * 12 * g.Vh + aos(k, cb, 12, g.Vh);
     if (unpack) dst[ci] = src[si];
     else dst[si] = src[ci];
   }
@@ -314,13 +374,19 @@ __global__ void k_axpby(long long n, double2* y, double a, const double2* x, dou
   double2 xv = x[i], yv = y[i];
   y[i] = make_double2(a * xv.x + b * yv.x, a * xv.y + b * yv.y);
 }
-__global__ void k_gamma5(long long n, int Vh, double2* y, const double2* x) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int comp = (int)((i / Vh) % 12);
-  const double s = comp < 6 ? -1.0 : 1.0;   // gamma_5 = diag(-1, -1, 1, 1)
-  double2 v = x[i];
-  y[i] = make_double2(s * v.x, s * v.y);
+// y = gamma_5 x = diag(-1, -1, 1, 1) x on nhalf half fields, site by site
+__global__ void k_gamma5(int Vh, int nhalf, double2* y, const double2* x) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)Vh * nhalf) return;
+  const int f = (int)(idx / Vh), i = (int)(idx - (long long)f * Vh);
+  SpinorF64 X{(double2*)x + (size_t)f * 12 * Vh, Vh}, Y{y + (size_t)f * 12 * Vh, Vh};
+  Spinor<double> s;
+  X.load(i, s);
+  for (int c = 0; c < 3; ++c) {
+    s.c[0][c] = -s.c[0][c];
+    s.c[1][c] = -s.c[1][c];
+  }
+  Y.store(i, s);
 }
 __global__ void k_fill(long long n, unsigned int* p) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -349,8 +415,8 @@ whmc_status copy_f64(whmc_ctx* c, double* y, const double* x, int nhalf) {
   return WHMC_OK;
 }
 whmc_status gamma5_f64(whmc_ctx* c, double* y, const double* x, int nhalf) {
-  const long long n = 12LL * c->Vh * nhalf;
-  hipLaunchKernelGGL(k_gamma5, flat_grid(n), dim3(256), 0, c->stream, n, c->Vh, (double2*)y, (const double2*)x);
+  const long long n = (long long)c->Vh * nhalf;
+  hipLaunchKernelGGL(k_gamma5, flat_grid(n), dim3(256), 0, c->stream, c->Vh, nhalf, (double2*)y, (const double2*)x);
   WHMC_HIP(hipGetLastError());
   return WHMC_OK;
 }
@@ -573,11 +639,7 @@ whmc_status whmc_apply_H(whmc_ctx* c, void* out, const void* in, int out_parity,
   WHMC_CHECK(links == WHMC_L12 || links == WHMC_L18, WHMC_EARG, "whmc_apply_H: links must be 12 or 18");
   const int dag = dagger ? 1 : 0;
   if (out_parity >= 0) return hop(c, prec, links, out_parity, dag, out, in, nullptr, 0.0, 1.0, nullptr, true);
-  const size_t hb = half_bytes(prec, c->Vh);
-  const char* ic = (const char*)in;
-  char* oc = (char*)out;
-  WHMC_TRY(hop(c, prec, links, 0, dag, oc, ic + hb, nullptr, 0.0, 1.0, nullptr, true));
-  return hop(c, prec, links, 1, dag, oc + hb, ic, nullptr, 0.0, 1.0, nullptr, true);
+  return hop_full(c, prec, links, dag, out, in);
 }
 
 whmc_status whmc_apply_Moo(whmc_ctx* c, double* out, const double* in, double kappa, int dagger) {

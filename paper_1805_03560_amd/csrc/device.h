@@ -1,16 +1,17 @@
 // Device-side building blocks for the Wilson hot path on gfx950: complex and SU(3) arithmetic,
 // the storage formats of spinors and links in every precision, and checkerboard geometry.
 //
-// Storage (all structure-of-arrays over the V/2 sites of one parity, so that 64 consecutive
-// lanes of a wavefront touch 64 consecutive 8/16-byte words):
-//   spinor F64 : double2 [12][Vh]            component c = 3*spin + colour, one complex each
-//   spinor F32 : float4  [6][Vh]             two complex components per float4
-//   spinor F16 : uint4   [3][Vh] + float [Vh] four complex (8 halves) per uint4, values divided
-//                                             by the per-site scale (max |component|)
-//   link  F64-18 : double2 [2][4][9][Vh]     [parity of x][mu][row*3+col][cb(x)] holds U_{x,mu}
-//   link  F64-12 : double2 [2][4][6][Vh]     rows 0 and 1; row 2 = conj(row0 x row1)
-//   link  F32-12 : float4  [2][4][3][Vh]     rows 0,1 as 3 float4 (2 complex each)
-//   link  F16-12 : uint2   [2][4][3][Vh]     rows 0,1 as 3 x (4 halves = 2 complex)
+// Storage (over the V/2 sites of one parity, in 64-site AoSoA blocks -- see aos() -- so that the
+// 64 lanes of a wavefront touch 64 consecutive 8/16-byte words of one component):
+//   spinor F64 : double2, 12 components      component c = 3*spin + colour, one complex each
+//   spinor F32 : float4, 6 components        two complex components per float4
+//   spinor F16 : uint4, 3 components, then float [Vh] per-site scales (max |component|); four
+//                                             complex (8 halves) per uint4, divided by the scale
+//   link  F64-18 : double2 [2][4] x 9 comps  [parity of x][mu] block of U_{x,mu}[row*3+col]
+//   link  F64-12 : double2 [2][4] x 6 comps  rows 0 and 1; row 2 = conj(row0 x row1)
+//   link  F32-18 : float2  [2][4] x 9 comps
+//   link  F32-12 : float4  [2][4] x 3 comps  rows 0,1 as 3 float4 (2 complex each)
+//   link  F16-12 : uint2   [2][4] x 3 comps  rows 0,1 as 3 x (4 halves = 2 complex)
 // Link entries are bounded by 1 in modulus, so half precision links need no scale.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -190,6 +191,18 @@ WHMC_DEV int xcd_remap(int B, int nb) {
   return k * q + (k < r ? k : r) + m;
 }
 
+// ------------------------------------------------------------------ AoSoA addressing
+// Per-site fields with K components over n sites are stored in blocks of 64 sites (one
+// wavefront): component k of site i lives at (i/64)*64*K + k*w + i%64, with w = 64 for full blocks
+// and w = n%64 for the last, partial block.  A wavefront's load of one component is a single
+// contiguous 1 KiB (FP64) run, the fields of a block share DRAM pages, and a field occupies
+// exactly K*n elements for any n.
+WHMC_DEV size_t aos(int k, int i, int K, int n) {
+  const int blk = i >> 6;
+  const int w = blk < (n >> 6) ? 64 : (n & 63);
+  return (size_t)blk * 64 * K + (size_t)k * w + (i & 63);
+}
+
 // ------------------------------------------------------------------ spinor storage
 struct SpinorF64 {
   using Real = double;
@@ -198,7 +211,7 @@ struct SpinorF64 {
   WHMC_DEV void load(int i, Spinor<double>& s) const {
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      double2 v = p[(size_t)k * stride + i];
+      double2 v = p[aos(k, i, 12, stride)];
       s.c[k / 3][k % 3] = {v.x, v.y};
     }
   }
@@ -206,7 +219,7 @@ struct SpinorF64 {
   WHMC_DEV void store(int i, const Spinor<double>& s) const {
 #pragma unroll
     for (int k = 0; k < 12; ++k)
-      stg<NT>(p + (size_t)k * stride + i, make_double2(s.c[k / 3][k % 3].re, s.c[k / 3][k % 3].im));
+      stg<NT>(p + aos(k, i, 12, stride), make_double2(s.c[k / 3][k % 3].re, s.c[k / 3][k % 3].im));
   }
 };
 
@@ -217,7 +230,7 @@ struct SpinorF32 {
   WHMC_DEV void load(int i, Spinor<float>& s) const {
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      float4 v = p[(size_t)k * stride + i];
+      float4 v = p[aos(k, i, 6, stride)];
       s.c[(2 * k) / 3][(2 * k) % 3] = {v.x, v.y};
       s.c[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v.z, v.w};
     }
@@ -227,7 +240,7 @@ struct SpinorF32 {
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       cplx<float> a = s.c[(2 * k) / 3][(2 * k) % 3], b = s.c[(2 * k + 1) / 3][(2 * k + 1) % 3];
-      stg<NT>(p + (size_t)k * stride + i, make_float4(a.re, a.im, b.re, b.im));
+      stg<NT>(p + aos(k, i, 6, stride), make_float4(a.re, a.im, b.re, b.im));
     }
   }
 };
@@ -244,7 +257,7 @@ struct SpinorF16 {
     float sc = scale[i];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      uint4 v = p[(size_t)k * stride + i];
+      uint4 v = p[aos(k, i, 3, stride)];
       unsigned int w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -271,7 +284,7 @@ struct SpinorF16 {
         w[j] = (unsigned int)f2h(inv * s.c[comp / 3][comp % 3].re) |
                ((unsigned int)f2h(inv * s.c[comp / 3][comp % 3].im) << 16);
       }
-      stg<NT>(p + (size_t)k * stride + i, make_uint4(w[0], w[1], w[2], w[3]));
+      stg<NT>(p + aos(k, i, 3, stride), make_uint4(w[0], w[1], w[2], w[3]));
     }
   }
 };
@@ -284,10 +297,10 @@ struct LinkF64_18T {
   const double2* p;
   int Vh;
   WHMC_DEV void load(int par, int mu, int i, SU3<double>& U) const {
-    const double2* q = p + ((size_t)(par * 4 + mu) * 9) * Vh + i;
+    const double2* q = p + (size_t)(par * 4 + mu) * 9 * Vh;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      double2 v = ldg<NT>(q + (size_t)k * Vh);
+      double2 v = ldg<NT>(q + aos(k, i, 9, Vh));
       U.e[k / 3][k % 3] = {v.x, v.y};
     }
   }
@@ -299,10 +312,10 @@ struct LinkF64_12T {
   const double2* p;
   int Vh;
   WHMC_DEV void load(int par, int mu, int i, SU3<double>& U) const {
-    const double2* q = p + ((size_t)(par * 4 + mu) * 6) * Vh + i;
+    const double2* q = p + (size_t)(par * 4 + mu) * 6 * Vh;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      double2 v = ldg<NT>(q + (size_t)k * Vh);
+      double2 v = ldg<NT>(q + aos(k, i, 6, Vh));
       U.e[k / 3][k % 3] = {v.x, v.y};
     }
     reconstruct_row2(U);
@@ -315,10 +328,10 @@ struct LinkF32_12T {
   const float4* p;
   int Vh;
   WHMC_DEV void load(int par, int mu, int i, SU3<float>& U) const {
-    const float4* q = p + ((size_t)(par * 4 + mu) * 3) * Vh + i;
+    const float4* q = p + (size_t)(par * 4 + mu) * 3 * Vh;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      float4 v = ldg<NT>(q + (size_t)k * Vh);
+      float4 v = ldg<NT>(q + aos(k, i, 3, Vh));
       U.e[(2 * k) / 3][(2 * k) % 3] = {v.x, v.y};
       U.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v.z, v.w};
     }
@@ -332,10 +345,10 @@ struct LinkF32_18T {
   const float2* p;
   int Vh;
   WHMC_DEV void load(int par, int mu, int i, SU3<float>& U) const {
-    const float2* q = p + ((size_t)(par * 4 + mu) * 9) * Vh + i;
+    const float2* q = p + (size_t)(par * 4 + mu) * 9 * Vh;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      float2 v = ldg<NT>(q + (size_t)k * Vh);
+      float2 v = ldg<NT>(q + aos(k, i, 9, Vh));
       U.e[k / 3][k % 3] = {v.x, v.y};
     }
   }
@@ -347,10 +360,10 @@ struct LinkF16_12T {
   const uint2* p;
   int Vh;
   WHMC_DEV void load(int par, int mu, int i, SU3<float>& U) const {
-    const uint2* q = p + ((size_t)(par * 4 + mu) * 3) * Vh + i;
+    const uint2* q = p + (size_t)(par * 4 + mu) * 3 * Vh;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      uint2 v = ldg<NT>(q + (size_t)k * Vh);
+      uint2 v = ldg<NT>(q + aos(k, i, 3, Vh));
       U.e[(2 * k) / 3][(2 * k) % 3] = {h2f((unsigned short)(v.x & 0xffffu)), h2f((unsigned short)(v.x >> 16))};
       U.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {h2f((unsigned short)(v.y & 0xffffu)), h2f((unsigned short)(v.y >> 16))};
     }

@@ -342,13 +342,13 @@ __global__ __launch_bounds__(kBlock) void k_link_update(int Vh, double2* U18, co
   SU3<double> A, E, U, N;
   from_coords(a, A);
   expm3(A, E);
-  double2* q = U18 + ((size_t)pm * 9) * Vh + i;
+  double2* q = U18 + (size_t)pm * 9 * Vh;
   for (int k = 0; k < 9; ++k) {
-    double2 v = q[(size_t)k * Vh];
+    double2 v = q[aos(k, i, 9, Vh)];
     U.e[k / 3][k % 3] = {v.x, v.y};
   }
   matmul(E, U, N);
-  for (int k = 0; k < 9; ++k) q[(size_t)k * Vh] = make_double2(N.e[k / 3][k % 3].re, N.e[k / 3][k % 3].im);
+  for (int k = 0; k < 9; ++k) q[aos(k, i, 9, Vh)] = make_double2(N.e[k / 3][k % 3].re, N.e[k / 3][k % 3].im);
 }
 
 whmc_status link_update(whmc_ctx* c, const double* pi, double eps) {
