@@ -31,7 +31,7 @@ template <class Lnk, class S>
 __global__ __launch_bounds__(kBlock) void k_cg1(Geom g, Lnk L, S p, S t, const CGScalars* sc) {
   if (halted(sc)) return;
   using R = typename S::Real;
-  const int i = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int i = site_block(g, blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (i >= g.Vh) return;
   Spinor<R> acc;
   hop_site<0>(g, 0, i, L, p, acc);
@@ -42,7 +42,7 @@ template <class Lnk, class S>
 __global__ __launch_bounds__(kBlock) void k_cg2(Geom g, Lnk L, S t, S p, S u, double k2, CGScalars* sc, Reduce red) {
   if (halted(sc)) return;
   using R = typename S::Real;
-  const int i = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int i = site_block(g, blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   double nrm = 0.0;
   if (i < g.Vh) {
     Spinor<R> acc, pv;
@@ -76,7 +76,7 @@ template <class Lnk, class S>
 __global__ __launch_bounds__(kBlock) void k_cg3(Geom g, Lnk L, S u, S v, const CGScalars* sc) {
   if (halted(sc)) return;
   using R = typename S::Real;
-  const int i = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int i = site_block(g, blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (i >= g.Vh) return;
   Spinor<R> acc;
   hop_site<1>(g, 0, i, L, u, acc);
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_cg4(Geom g, Lnk L, S v, S u, S p, SR
   if (halted(sc)) return;
   using R = typename S::Real;
   using RR = typename SR::Real;
-  const int i = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int i = site_block(g, blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   const double alpha = sc->alpha;
   double nrm = 0.0;
   if (i < g.Vh) {

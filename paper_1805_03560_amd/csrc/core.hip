@@ -37,7 +37,7 @@ template <int DAG, bool XPAY, bool NORM, bool NTS, class Lnk, class SIn, class S
 __global__ __launch_bounds__(kBlock) void k_hop(Geom g, int par, Lnk L, SIn in, SX x, SOut out, double a,
                                                 double b, Reduce red, double* norm_out) {
   using R = typename SOut::Real;
-  const int i = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int i = site_block(g, blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   double nrm = 0.0;
   if (i < g.Vh) {
     Spinor<R> acc;
@@ -108,14 +108,13 @@ static whmc_status hop_nt(whmc_ctx* c, int prec, int links, int par, int dag, vo
                     b, norm_out, nts);
 }
 
-// Full-lattice H in one launch: logical block b applies the parity-(b & 1) block of H to the sites
-// of region b >> 1, so each XCD works on both parities of its contiguous region.
+// Full-lattice H in one launch of 2 nb workgroups: each XCD applies both parity blocks of H to the
+// sites of its own region.
 template <int DAG, bool NTS, class Lnk, class S>
 __global__ __launch_bounds__(kBlock) void k_hop_full(Geom g, Lnk L, S in_e, S in_o, S out_e, S out_o) {
   using R = typename S::Real;
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int par = b & 1;
-  const int i = (b >> 1) * kBlock + threadIdx.x;
+  int par;
+  const int i = site_block_pair(g, blockIdx.x, gridDim.x >> 1, par) * kBlock + threadIdx.x;
   if (i >= g.Vh) return;
   Spinor<R> acc;
   hop_site<DAG>(g, par, i, L, par ? in_e : in_o, acc);
@@ -507,6 +506,10 @@ whmc_status whmc_create(whmc_ctx** out, const int dims[4], int device, void* str
   c->Vh = (int)(V / 2);
   c->g.Vh = c->Vh;
   c->g.Lxh = dims[3] / 2;
+  {
+    const long long slice = (long long)dims[1] * dims[2] * dims[3] / 2;
+    c->g.xq = slice % (8 * kBlock) == 0 ? (int)(slice / (8 * kBlock)) : 0;
+  }
   c->device = device;
   c->stream = (hipStream_t)stream;
   const size_t nlinks = (size_t)8 * c->Vh;

@@ -97,6 +97,7 @@ struct Geom {
   int L[4];
   int Vh;
   int Lxh;   // L_x / 2
+  int xq;    // blocks per XCD per time slice for site_block (0: slices do not split evenly)
 };
 
 struct Coords {
@@ -189,6 +190,32 @@ template <bool NT> WHMC_DEV void stg(uint4* p, uint4 v) {
 WHMC_DEV int xcd_remap(int B, int nb) {
   const int k = B & 7, m = B >> 3, q = nb >> 3, r = nb & 7;
   return k * q + (k < r ? k : r) + m;
+}
+
+// Workgroup -> block of sites for the stencil kernels (one block per workgroup, nb blocks cover the
+// Vh sites of one parity).  A time slice is a contiguous range of cb indices.  When every slice
+// splits into 8 equal ranges of whole blocks (g.xq blocks each, nb = 8 * g.xq * L_t), XCD k takes
+// range k of every slice and sweeps t upwards: an input spinor is then read by its t-1 and t+1
+// neighbours a few slice-ranges apart, while both are in the same L2, instead of a whole slice of
+// the lattice apart.  Otherwise XCD k takes the k-th contiguous eighth of the blocks.
+WHMC_DEV int site_block(const Geom& g, int B, int nb) {
+  if (g.xq == 0) return xcd_remap(B, nb);
+  const int k = B & 7, m = B >> 3;
+  const int t = m / g.xq, j = m - t * g.xq;
+  return (t * 8 + k) * g.xq + j;
+}
+
+// Both parities in one grid of 2 nb workgroups: the XCD's m-th workgroup does parity m & 1 of its
+// (m >> 1)-th block, so each XCD applies both parities to the same region.
+WHMC_DEV int site_block_pair(const Geom& g, int B, int nb, int& par) {
+  const int k = B & 7, m = B >> 3;
+  if (g.xq == 0) {
+    const int b = xcd_remap(B, 2 * nb);
+    par = b & 1;
+    return b >> 1;
+  }
+  par = m & 1;
+  return site_block(g, ((m >> 1) << 3) | k, nb);
 }
 
 // ------------------------------------------------------------------ AoSoA addressing

@@ -106,7 +106,7 @@ template <int DAG, int NB, class Lnk, class S>
 __global__ __launch_bounds__(kBlock) void k_mhop(Geom g, int par, int nrhs, Lnk L, S in0, S out0) {
   using R = typename S::Real;
   const int r0 = blockIdx.y * NB;
-  const int i = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int i = site_block(g, blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (i >= g.Vh) return;
   bool act[NB];
   S in[NB];
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void k_mcg1(Geom g, int nrhs, Lnk L, S p0, 
 #pragma unroll
   for (int k = 0; k < NB; ++k) { act[k] = rhs_live(sc, r0 + k, nrhs); any |= act[k]; }
   if (!any) return;
-  const int i = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int i = site_block(g, blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (i >= g.Vh) return;
   S in[NB];
 #pragma unroll
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_mcg2(Geom g, int nrhs, Lnk L, S t0, 
 #pragma unroll
   for (int k = 0; k < NB; ++k) { act[k] = rhs_live(sc, r0 + k, nrhs); any |= act[k]; }
   if (!any) return;
-  const int i = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int i = site_block(g, blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   double nrm[NB];
 #pragma unroll
   for (int k = 0; k < NB; ++k) nrm[k] = 0.0;
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_mcg3(Geom g, int nrhs, Lnk L, S u0, 
 #pragma unroll
   for (int k = 0; k < NB; ++k) { act[k] = rhs_live(sc, r0 + k, nrhs); any |= act[k]; }
   if (!any) return;
-  const int i = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int i = site_block(g, blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (i >= g.Vh) return;
   S in[NB];
 #pragma unroll
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_mcg4(Geom g, int nrhs, Lnk L, S v0, 
 #pragma unroll
   for (int k = 0; k < NB; ++k) { act[k] = rhs_live(sc, r0 + k, nrhs); any |= act[k]; }
   if (!any) return;
-  const int i = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int i = site_block(g, blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   double nrm[NB];
 #pragma unroll
   for (int k = 0; k < NB; ++k) nrm[k] = 0.0;

@@ -17,8 +17,8 @@ KAPPAS = [0.150, 0.153, 0.156, 0.1575]
 
 @pytest.mark.parametrize("nrhs", [1, 3, 5])
 @pytest.mark.parametrize("nb", [1, 2, 3, 4])
-def test_multi_hop_fp64_parity(nrhs, nb):
-    dims = (4, 4, 6, 6)
+@pytest.mark.parametrize("dims", [(4, 4, 6, 6), (4, 8, 16, 16)])
+def test_multi_hop_fp64_parity(nrhs, nb, dims):
     lat = Lattice(dims)
     U = synth.haar_links(dims, 5000)
     xs = np.stack([synth.gaussian_spinor(lat.Vh, 5001 + r) for r in range(nrhs)])
@@ -54,9 +54,10 @@ def test_autotuner_returns_a_valid_block():
     assert ctx.autotune(whmc.F64, whmc.L18, 8)[0] == nb     # remembered
 
 
-@pytest.mark.parametrize("prec,nrhs,nb", [(whmc.F64, 4, 0), (whmc.F64, 5, 2), (whmc.F32, 4, 0), (whmc.F16, 6, 3)])
-def test_masked_multi_rhs_cg(prec, nrhs, nb):
-    dims = (4, 4, 4, 8)
+@pytest.mark.parametrize("prec,nrhs,nb,dims", [(whmc.F64, 4, 0, (4, 4, 4, 8)), (whmc.F64, 5, 2, (4, 4, 4, 8)),
+                                               (whmc.F32, 4, 0, (4, 4, 4, 8)), (whmc.F16, 6, 3, (4, 4, 4, 8)),
+                                               (whmc.F64, 2, 2, (4, 8, 16, 16))])
+def test_masked_multi_rhs_cg(prec, nrhs, nb, dims):
     lat = Lattice(dims)
     U = synth.smooth_links(dims, 5030)
     kappas = [KAPPAS[r % 4] for r in range(nrhs)]

@@ -3,6 +3,8 @@
 Tolerances: operator applications 1e-12 relative; solves are run to 1e-13/1e-14 on both sides,
 so solutions agree to ~cond(A) x 1e-13 (cond ~ 10-100 on these fields); forces that go through
 solves to 1e-10 relative; mixed-precision solves must reach the same 1e-10 true FP64 residual."""
+import functools
+
 import numpy as np
 import pytest
 
@@ -16,7 +18,8 @@ from gpu_util import algebra_to_numpy, make_ctx, pack_half, rel_err, to_dev, unp
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("dims,gen", [((4, 4, 4, 4), "haar"), ((8, 4, 4, 8), "smooth")])
+# (4, 8, 16, 16): time slices of 8 x 128 sites, the per-XCD slice schedule of the large lattices
+@pytest.mark.parametrize("dims,gen", [((4, 4, 4, 4), "haar"), ((8, 4, 4, 8), "smooth"), ((4, 8, 16, 16), "smooth")])
 def test_cg_fp64_parity(dims, gen):
     lat = Lattice(dims)
     U = synth.haar_links(dims, 2000) if gen == "haar" else synth.smooth_links(dims, 2000)
@@ -34,14 +37,21 @@ def test_cg_fp64_parity(dims, gen):
     assert rel_err(unpack_half(ctx, x), ref) < 1e-8
 
 
-@pytest.mark.parametrize("prec,links", [(whmc.F32, whmc.L12), (whmc.F32, whmc.L18), (whmc.F16, whmc.L12)])
-def test_mixed_cg_reaches_fp64_residual(prec, links):
-    dims = (8, 4, 4, 8)
+@functools.lru_cache(maxsize=None)
+def _mixed_case(dims):
+    """Links, source and FP64 oracle solution (to 1e-14) shared by the mixed-precision cases."""
     lat = Lattice(dims)
     U = synth.smooth_links(dims, 2010)
     b = synth.gaussian_spinor(lat.Vh, 2011)
+    ref, _, _ = cg(lambda v: dirac.apply_MooDagMoo(lat, U, v, 0.1575), b, tol=1e-14)
+    return U, b, ref
+
+
+@pytest.mark.parametrize("prec,links", [(whmc.F32, whmc.L12), (whmc.F32, whmc.L18), (whmc.F16, whmc.L12)])
+@pytest.mark.parametrize("dims", [(8, 4, 4, 8), (4, 8, 16, 16)])
+def test_mixed_cg_reaches_fp64_residual(prec, links, dims):
+    U, b, ref = _mixed_case(dims)
     kappa = 0.1575
-    ref, _, _ = cg(lambda v: dirac.apply_MooDagMoo(lat, U, v, kappa), b, tol=1e-14)
     ctx = make_ctx(dims, U)
     x, st = ctx.cg_solve(pack_half(ctx, b), [kappa], whmc.cg_params(tol=1e-10, prec=prec, links=links, delta=0.1))
     assert st[0]["converged"] and st[0]["true_residual"] <= 1e-10
