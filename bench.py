@@ -251,22 +251,17 @@ def multi_rhs(whmc, torch, stream):
         b = ctx.pack_spinor(torch.from_numpy(bs).to(ctx.device), 0)
         kappas = [kp[r % 4] for r in range(nrhs)]
         row = {}
-        # batched hop, FP64 18-real (autotuned register block) vs nrhs single hops
-        nb, _ = ctx.autotune(whmc.F64, whmc.L18, nrhs)
-        o = ctx.half_spinor(whmc.F64, nrhs)
-        ms = time_events(lambda: ctx.apply_H_multi(b, 0, nrhs, out=o, rhs_block=nb), stream, torch, reps=10)
-        bytes_launch = Vh * (1152 + 384 * nrhs)
-        row["hop_f64_rhs_block"] = nb
-        row["hop_f64_us_per_rhs"] = round(ms * 1e3 / nrhs, 2)
-        row["hop_f64_GBps"] = round(bytes_launch / (ms * 1e-3) / 1e9, 1)
-        nb32, _ = ctx.autotune(whmc.F32, whmc.L12, nrhs)
-        b32 = ctx.convert_spinor(b, whmc.F64, whmc.F32, nrhs)
-        o32 = ctx.half_spinor(whmc.F32, nrhs)
-        ms32 = time_events(lambda: ctx.apply_H_multi(b32, 0, nrhs, prec=whmc.F32, links=whmc.L12, out=o32,
-                                                     rhs_block=nb32), stream, torch, reps=10)
-        row["hop_f32_l12_rhs_block"] = nb32
-        row["hop_f32_l12_us_per_rhs"] = round(ms32 * 1e3 / nrhs, 2)
-        row["hop_f32_l12_GBps"] = round(Vh * (576 + 192 * nrhs) / (ms32 * 1e-3) / 1e9, 1)
+        # batched hop per format (autotuned blocking: rhs per thread x lanes per site)
+        for pn, p, links, lb, sb in [("f64", whmc.F64, whmc.L18, 1152, 384), ("f32_l12", whmc.F32, whmc.L12, 384, 192),
+                                     ("f16_l12", whmc.F16, whmc.L12, 192, 104)]:
+            nb, lanes, _ = ctx.autotune(p, links, nrhs)
+            bp = b if p == whmc.F64 else ctx.convert_spinor(b, whmc.F64, p, nrhs)
+            o = ctx.half_spinor(p, nrhs)
+            ms = time_events(lambda: ctx.apply_H_multi(bp, 0, nrhs, prec=p, links=links, out=o, rhs_block=nb,
+                                                       rhs_lanes=lanes), stream, torch, reps=10)
+            row[f"hop_{pn}_blocking"] = [nb, lanes]
+            row[f"hop_{pn}_us_per_rhs"] = round(ms * 1e3 / nrhs, 2)
+            row[f"hop_{pn}_GBps"] = round(Vh * (lb + sb * nrhs) / (ms * 1e-3) / 1e9, 1)
         # CG to 1e-10: sequential FP64, masked multi-RHS FP64, masked multi-RHS mixed FP32-12
         def seq():
             for r in range(nrhs):
@@ -293,7 +288,9 @@ def multi_rhs(whmc, torch, stream):
                          "max_rel_err_vs_fp64_1e-12": err}
         row["sequential_fp64_ms"] = round(t_seq, 2)
         res[f"nrhs{nrhs}"] = row
-        log(f"[bench] multi-RHS {nrhs}: hop {row['hop_f64_us_per_rhs']} us/rhs (nb {nb}), seq {t_seq:.1f} ms, "
+        log(f"[bench] multi-RHS {nrhs}: hop us/rhs f64 {row['hop_f64_us_per_rhs']} {row['hop_f64_blocking']}, f32 "
+            f"{row['hop_f32_l12_us_per_rhs']} {row['hop_f32_l12_blocking']}, f16 {row['hop_f16_l12_us_per_rhs']} "
+            f"{row['hop_f16_l12_blocking']}; seq {t_seq:.1f} ms, "
             f"multi fp64 {row['multi_fp64']['ms']} ms, mixed f32 {row['multi_mixed_f32_l12']['ms']} ms, "
             f"mixed f16 {row['multi_mixed_f16_l12']['ms']} ms")
     ctx.close()

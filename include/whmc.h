@@ -111,17 +111,22 @@ whmc_status whmc_unpack_algebra(whmc_ctx* ctx, double* dst, const double* src);
 whmc_status whmc_apply_H(whmc_ctx* ctx, void* out, const void* in, int out_parity, int dagger, int prec, int links);
 
 /* Multi right-hand-side form of the even/odd hop: out_r = H_{p,1-p} in_r for r < nrhs (nrhs
- * consecutive half fields in and out, 1 <= nrhs <= 16).  Each link is loaded once per block of
- * rhs_block right-hand sides (1..4; 0 = the autotuned block).  Formats: FP64 with 18- or 12-real
- * links, FP32 and FP16 with 12-real links. */
+ * consecutive half fields in and out, 1 <= nrhs <= 16).  Blocking: each thread applies the links
+ * of its site to rhs_block right-hand sides held in registers (one link load and decode serves
+ * them all), and rhs_lanes lanes of a wavefront hold the same site for further right-hand sides,
+ * sharing each link load instruction; the groups of right-hand sides of a site block run back to
+ * back on one XCD so the links are reused from its L2.  Allowed: FP64 (18- or 12-real links)
+ * rhs_block = 1 with rhs_lanes = 1, 2 or 4; FP32 / FP16 (12-real links) rhs_block = 1, 2 or 4
+ * with rhs_lanes = 1 or 2.  rhs_block = rhs_lanes = 0 takes the autotuned blocking; one of them 0
+ * reads as 1; anything else is WHMC_EARG. */
 whmc_status whmc_apply_H_multi(whmc_ctx* ctx, void* out, const void* in, int out_parity, int dagger, int prec,
-                               int links, int nrhs, int rhs_block);
+                               int links, int nrhs, int rhs_block, int rhs_lanes);
 
-/* Autotuner: time the multi-RHS hop for every register block 1..min(4, nrhs) at this lattice
- * size, precision and link format, remember the fastest in the context and return it (and its
- * time per launch in microseconds if us != NULL).  Later calls with the same key return the
- * stored choice without timing. */
-whmc_status whmc_autotune(whmc_ctx* ctx, int prec, int links, int nrhs, int* rhs_block, double* us);
+/* Autotuner: time the multi-RHS hop for every allowed blocking not wider than needed for nrhs
+ * at this lattice size, precision and link format, remember the fastest in the context and
+ * return it (and its time per launch in microseconds if us != NULL).  Later calls with the same
+ * key return the stored choice without timing. */
+whmc_status whmc_autotune(whmc_ctx* ctx, int prec, int links, int nrhs, int* rhs_block, int* rhs_lanes, double* us);
 
 /* out = M_oo in = in - kappa^2 H_oe H_eo in (dagger = 0) or M_oo^dag in (dagger = 1), FP64,
  * odd-site half fields (Sec. 2.2).  Uses context scratch for the even-site intermediate. */
@@ -138,9 +143,10 @@ whmc_status whmc_apply_MdagM(whmc_ctx* ctx, double* out, const double* in, const
  *     format and `links`-real links of the same precision, FP64 reliable updates recompute
  *     r = b - A x whenever the iterated residual drops below delta times its maximum since the
  *     last update; dot products accumulate in FP64.
- *   nrhs > 1: all right-hand sides advance together through multi-RHS kernels that load each
- *     link once per block of rhs_block right-hand sides (0 = autotuned); a converged rhs is
- *     frozen (masked) while the others continue.
+ *   nrhs > 1: all right-hand sides advance together through the multi-RHS kernels, blocked as
+ *     in whmc_apply_H_multi (rhs_block = rhs_lanes = 0: autotuned); a converged rhs is frozen
+ *     (masked) while the others continue; the FP64 true residuals of reliable updates and of
+ *     the final check are computed for all right-hand sides concerned in one multi-RHS pass.
  * stats (may be NULL) receives nrhs entries.  Returns ENOCONV if any rhs misses tol. */
 typedef struct whmc_cg_params {
   double tol;         /* target true relative residual, e.g. 1e-10 */
@@ -149,7 +155,8 @@ typedef struct whmc_cg_params {
   int links;          /* whmc_links of the bulk operator */
   double delta;       /* reliable-update trigger (mixed only), e.g. 0.1 */
   int check_every;    /* iterations enqueued between host convergence checks (>= 1) */
-  int rhs_block;      /* multi-RHS register block, 0 = autotuned */
+  int rhs_block;      /* multi-RHS register block (right-hand sides per thread), 0 = autotuned */
+  int rhs_lanes;      /* multi-RHS lanes per site sharing link loads, 0 = autotuned */
 } whmc_cg_params;
 
 typedef struct whmc_cg_stats {

@@ -274,7 +274,7 @@ static SpinorF16 s16(void* p, int Vh) { return SpinorF16{(uint4*)p, (float*)((ui
 
 template <class Lnk, class S, class SR, bool MIXED>
 static whmc_status enqueue_iters(whmc_ctx* c, const Lnk& L, S p, S t, S u, S v, SR r, SR x, double kappa, int n) {
-  const dim3 grid(c->num_blocks()), block(kBlock);
+  const dim3 grid(c->stencil_blocks()), block(kBlock);
   const double k2 = kappa * kappa;
   for (int it = 0; it < n; ++it) {
     hipLaunchKernelGGL((k_cg1<Lnk, S>), grid, block, 0, c->stream, c->g, L, p, t, c->scal);
@@ -402,7 +402,7 @@ static whmc_status cg_mixed(whmc_ctx* c, double* x, const double* b, double kapp
                      prm->tol * prm->tol, prm->delta * prm->delta);
   WHMC_HIP(hipGetLastError());
   const int check = prm->check_every > 0 ? prm->check_every : 8;
-  const dim3 grid(c->num_blocks()), block(kBlock);
+  const dim3 grid(c->stencil_blocks()), block(kBlock);
   CGScalars hs{};
   int iters = 0;
   double rel = 1.0;

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kBlock) void k_hop(Geom g, int par, Lnk L, SIn in, 
 template <class Lnk, class S>
 static whmc_status launch_hop(whmc_ctx* c, const Lnk& L, int par, int dag, S in, S x, S out, bool xpay, double a,
                               double b, double* norm_out, bool nts) {
-  dim3 grid(c->num_blocks()), block(kBlock);
+  dim3 grid(c->stencil_blocks()), block(kBlock);
 #define WHMC_L(D, XP, N, NS) hipLaunchKernelGGL((k_hop<D, XP, N, NS, Lnk, S, S, S>), grid, block, 0, c->stream, c->g, \
                                                 par, L, in, x, out, a, b, c->red, norm_out)
   const bool norm = norm_out != nullptr;
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_hop_full(Geom g, Lnk L, S in_e, S in
 
 template <class Lnk, class S>
 static whmc_status launch_full(whmc_ctx* c, const Lnk& L, int dag, S ie, S io, S oe, S oo, bool nts) {
-  dim3 grid(2 * c->num_blocks()), block(kBlock);
+  dim3 grid(2 * c->stencil_blocks()), block(kBlock);
   if (dag) {
     if (nts) hipLaunchKernelGGL((k_hop_full<1, true, Lnk, S>), grid, block, 0, c->stream, c->g, L, ie, io, oe, oo);
     else hipLaunchKernelGGL((k_hop_full<1, false, Lnk, S>), grid, block, 0, c->stream, c->g, L, ie, io, oe, oo);
@@ -508,13 +508,16 @@ whmc_status whmc_create(whmc_ctx** out, const int dims[4], int device, void* str
   c->g.Lxh = dims[3] / 2;
   {
     const long long slice = (long long)dims[1] * dims[2] * dims[3] / 2;
-    c->g.xq = slice % (8 * kBlock) == 0 ? (int)(slice / (8 * kBlock)) : 0;
+    const bool split = slice % kBlock == 0 && slice / kBlock >= 8;
+    c->g.nbs = split ? (int)(slice / kBlock) : 0;
+    c->g.xq = split ? (c->g.nbs + 7) / 8 : 0;
   }
   c->device = device;
   c->stream = (hipStream_t)stream;
   const size_t nlinks = (size_t)8 * c->Vh;
   hipError_t e = hipMalloc(&c->U18, nlinks * 9 * sizeof(double2));
-  const int maxb = ((c->Vh + kBlock - 1) / kBlock) * (kMaxRhs + 4) + 1024 * kMaxRhs;
+  // partial sums: up to 8 rows per rhs (multi-RHS sub-blocks) of stencil_blocks() slots each
+  const int maxb = c->stencil_blocks() * (8 * kMaxRhs + 4) + 1024 * kMaxRhs;
   if (e == hipSuccess) e = hipMalloc(&c->red.partials, (size_t)maxb * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&c->red.counter, 64 * sizeof(unsigned));
   if (e == hipSuccess) e = hipMalloc(&c->red.result, 64 * sizeof(double));

@@ -97,7 +97,8 @@ struct Geom {
   int L[4];
   int Vh;
   int Lxh;   // L_x / 2
-  int xq;    // blocks per XCD per time slice for site_block (0: slices do not split evenly)
+  int nbs;   // blocks per time slice for site_block (0: a slice is not a whole number of blocks)
+  int xq;    // workgroups per XCD per time slice, ceil(nbs / 8); 0: plain eighths of the lattice
 };
 
 struct Coords {
@@ -192,17 +193,42 @@ WHMC_DEV int xcd_remap(int B, int nb) {
   return k * q + (k < r ? k : r) + m;
 }
 
-// Workgroup -> block of sites for the stencil kernels (one block per workgroup, nb blocks cover the
-// Vh sites of one parity).  A time slice is a contiguous range of cb indices.  When every slice
-// splits into 8 equal ranges of whole blocks (g.xq blocks each, nb = 8 * g.xq * L_t), XCD k takes
-// range k of every slice and sweeps t upwards: an input spinor is then read by its t-1 and t+1
-// neighbours a few slice-ranges apart, while both are in the same L2, instead of a whole slice of
-// the lattice apart.  Otherwise XCD k takes the k-th contiguous eighth of the blocks.
+// Workgroup -> block of sites for the stencil kernels.  A time slice is a contiguous range of cb
+// indices.  When a slice holds a whole number g.nbs >= 8 of blocks, it is cut into 8 ranges of
+// floor or ceil(g.nbs / 8) blocks, XCD k takes range k of every slice and sweeps t upwards: an
+// input spinor is then read by its t-1 and t+1 neighbours a few ranges apart, while both are in the
+// same L2, instead of a whole slice of the lattice apart.  The grid then has nb = 8 * g.xq * L_t
+// workgroups, g.xq = ceil(g.nbs / 8); a workgroup beyond its XCD's range gets the block index
+// L_t * g.nbs, whose sites all lie past the last site.  Otherwise (g.xq = 0, nb = ceil(Vh / block))
+// XCD k takes the k-th contiguous eighth of the blocks.
 WHMC_DEV int site_block(const Geom& g, int B, int nb) {
   if (g.xq == 0) return xcd_remap(B, nb);
   const int k = B & 7, m = B >> 3;
   const int t = m / g.xq, j = m - t * g.xq;
-  return (t * 8 + k) * g.xq + j;
+  const int lo = k * g.nbs / 8, hi = (k + 1) * g.nbs / 8;
+  if (lo + j >= hi) return g.L[0] * g.nbs;
+  return t * g.nbs + lo + j;
+}
+
+// G groups (e.g. of right-hand sides) per block of sites in one 1D grid of nb = G * (site grid)
+// workgroups: the G groups of a block run back to back on the same XCD.  grp receives the group;
+// slot numbers the workgroups of one group without repeats in [0, nb / G).
+WHMC_DEV int site_block_grp(const Geom& g, int B, int nb, int G, int& grp, int& slot) {
+  if (g.xq == 0) {
+    const int b = xcd_remap(B, nb);
+    slot = b / G;
+    grp = b - slot * G;
+    return slot;
+  }
+  const int k = B & 7, m = B >> 3;
+  const int per_t = g.xq * G;
+  const int t = m / per_t, r = m - t * per_t;
+  const int j = r / G;
+  grp = r - j * G;
+  slot = (t * g.xq + j) * 8 + k;
+  const int lo = k * g.nbs / 8, hi = (k + 1) * g.nbs / 8;
+  if (lo + j >= hi) return g.L[0] * g.nbs;
+  return t * g.nbs + lo + j;
 }
 
 // Both parities in one grid of 2 nb workgroups: the XCD's m-th workgroup does parity m & 1 of its

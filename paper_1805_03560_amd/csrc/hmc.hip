@@ -66,6 +66,7 @@ static whmc_cg_params default_solver() {
   p.delta = 0.1;
   p.check_every = 8;
   p.rhs_block = 0;
+  p.rhs_lanes = 0;
   return p;
 }
 

@@ -77,7 +77,7 @@ struct whmc_ctx {
   bool derived_valid[4] = {false, false, false, false};  // U12, U32_18, U32_12, U16_12
   // scratch
   std::map<std::string, std::pair<void*, size_t>> ws;
-  std::map<std::string, std::pair<int, double>> tuned;   // autotuned multi-RHS register blocks
+  std::map<std::string, std::pair<int, double>> tuned;   // autotuned multi-RHS blockings (16 nb + lanes, us)
   whmc::Reduce red{};
   whmc::CGScalars* scal = nullptr;   // kMaxRhs entries
   whmc::CGScalars* scal_host = nullptr;  // pinned mirror
@@ -92,6 +92,8 @@ struct whmc_ctx {
     return (long long)8 * Vh * per > stream_threshold;
   }
   int num_blocks() const { return (Vh + whmc::kBlock - 1) / whmc::kBlock; }
+  // grid of the stencil kernels (site_block): may exceed num_blocks() by padding workgroups
+  int stencil_blocks() const { return g.xq ? 8 * g.xq * g.L[0] : num_blocks(); }
 };
 
 namespace whmc {
@@ -132,8 +134,6 @@ whmc_status cg_solve(whmc_ctx* c, double* x, const double* b, const double* kapp
                      const whmc_cg_params* p, whmc_cg_stats* st);
 
 // ---- multi-RHS (multi.hip)
-whmc_status mhop(whmc_ctx* c, int prec, int links, int par, int dag, int nrhs, int nb, void* out, const void* in);
-whmc_status autotune_rhs_block(whmc_ctx* c, int prec, int links, int nrhs, int* best_nb, double* best_us);
 
 // ---- gauge and force kernels (gauge.hip)
 whmc_status plaquette_sum(whmc_ctx* c, double* host_out);

@@ -1,19 +1,24 @@
 // Multi right-hand-side hopping matrix and masked CG.
 //
-// One launch applies H to N_rhs spinor fields: each thread owns one site and a register block of
-// NB right-hand sides, loads every link once and applies it to all NB projected neighbours, so the
-// link bytes (the bulk of the stencil's traffic) are amortised over NB fields; grid.y runs over
-// the blocks of right-hand sides.  Algorithmic bytes per site and rhs:
-// (8 link loads + NB (in + out) spinors) / NB.
+// One launch applies H to N_rhs spinor fields.  Each thread owns one (site, rhs) pair and does the
+// single-rhs arithmetic, so its register use is that of the single-rhs hop.  The right-hand sides
+// form G = ceil(N_rhs / R) groups of R = 1, 2, 4 or 8; a workgroup of kBlock threads covers
+// kBlock / R sites (part `sub` of a kBlock-site block) for the R right-hand sides of one group.  In
+// every wavefront the lanes of one site for the R right-hand sides issue the same link addresses
+// in the same load instruction, which the memory pipeline serves once, and the R * G workgroups of
+// a site block run back to back on the same XCD, where the links are still in its L2.
+// Algorithmic bytes per site and rhs: (8 link loads + N_rhs (in + out) spinors) / N_rhs.
 //
 // The CG runs every rhs with its own kappa (mass-preconditioning shifts) and its own device-side
-// scalars.  A converged (or paused, in mixed precision) rhs is masked: the kernels skip its loads,
-// arithmetic and stores while the others keep iterating, and a block whose rhs are all masked
-// exits at once.  The register block NB is chosen by the autotuner (timed on first use per
-// precision, link format and N_rhs) unless the caller fixes it.
+// scalars.  A converged (or paused, in mixed precision) rhs is masked: its threads skip loads,
+// arithmetic and stores while the others keep iterating, and a workgroup whose right-hand sides
+// are all masked exits at once.  R is chosen by the autotuner (timed on first use per precision,
+// link format and N_rhs) unless the caller fixes it.
 #include <chrono>
 #include <cmath>
 #include <string>
+#include <type_traits>
+#include <vector>
 
 #include "internal.h"
 #include "stencil.h"
@@ -32,22 +37,93 @@ struct K2 {
   double v[kMaxRhs];
 };
 
+// ------------------------------------------------------------------ lane layout
+// The right-hand sides form groups of R * NB.  The workgroups of a site block are numbered
+// u = grp * R + sub (sub fastest); wavefront w of workgroup (grp, sub) holds the sites
+// sub * kBlock / R + w * S + (0 .. S-1) of the block (S = 64 / R), and lane l has site ... + l % S
+// and the NB right-hand sides rb .. rb + NB - 1, rb = grp * R * NB + (l / S) * NB.
+template <int NB, int R>
+struct MLane {
+  int i;      // cb site index (>= Vh: padding workgroup or ragged tail)
+  int rb;     // first rhs of the lane's register block
+  int r0;     // first rhs of the workgroup's group
+  int sub;    // part of the site block
+  int slot;   // partial-sum slot of this workgroup among the workgroups of its (grp, sub)
+};
+
+template <int NB, int R>
+WHMC_DEV MLane<NB, R> mlane(const Geom& g, int G) {
+  constexpr int S = 64 / R;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  int u;
+  MLane<NB, R> m;
+  const int sb = site_block_grp(g, blockIdx.x, gridDim.x, G * R, u, m.slot);
+  const int grp = u / R;
+  m.sub = u - grp * R;
+  m.r0 = grp * R * NB;
+  m.rb = m.r0 + (l / S) * NB;
+  m.i = sb * kBlock + m.sub * (kBlock / R) + w * S + (l % S);
+  return m;
+}
+
+WHMC_DEV bool rhs_live(const CGScalars* sc, int r, int nrhs) { return r < nrhs && !(sc[r].done | sc[r].pause); }
+
+// which right-hand sides a launch works on: all of them ...
+struct AllRhs {
+  int nrhs;
+  WHMC_DEV bool operator()(int r) const { return r < nrhs; }
+};
+// ... those still iterating (device-side CG flags) ...
+struct ByScalars {
+  const CGScalars* sc;
+  int nrhs;
+  WHMC_DEV bool operator()(int r) const { return rhs_live(sc, r, nrhs); }
+};
+// ... or a set chosen by the host (bit r of mask)
+struct BySet {
+  unsigned mask;
+  int nrhs;
+  WHMC_DEV bool operator()(int r) const { return r < nrhs && ((mask >> r) & 1u); }
+};
+
+template <int N, class P>
+WHMC_DEV bool any_live(const P& live, int r0) {
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < N; ++q) any |= live(r0 + q);
+  return any;
+}
+
 // ------------------------------------------------------------------ per-rhs partial sums
-// pass 1: rhs r of this block's slice writes its block partial to partials[r * nb + block];
-// pass 2 (k_m*_fin, one block per rhs) adds the nb partials of rhs r in a fixed order.
-template <int BLOCK, int NB>
-WHMC_DEV void block_partials_multi(const double* v, double* partials, int r0, int nrhs) {
-  const int nb = gridDim.x;
+// pass 1: the workgroup sums each of its R * NB right-hand sides (lane shuffles inside the S-lane
+// run of that rhs, then the wavefronts in a fixed order) and writes rhs r's sum to row
+// r * R + sub, slot slot of partials (rows of nslots doubles: rhs r owns rows r * R .. r * R + R - 1);
+// pass 2 (k_m*_fin, one block per rhs) adds the R * nslots partials of rhs r in a fixed order.
+template <int NB, int R>
+WHMC_DEV void mpartials(const double* v, double* partials, const MLane<NB, R>& m, int nrhs, int nslots) {
+  constexpr int S = 64 / R, W = kBlock / 64;
+  __shared__ double lds[W][R * NB];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
-    __shared__ double lds[BLOCK / 64];
-    __syncthreads();
-    const double s = block_sum<BLOCK>(v[k], lds);
-    if (threadIdx.x == 0 && r0 + k < nrhs) partials[(size_t)(r0 + k) * nb + blockIdx.x] = s;
+    double x = v[k];
+#pragma unroll
+    for (int off = S / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (l % S == 0) lds[w][(l / S) * NB + k] = x;
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < R * NB && m.r0 + t < nrhs) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) s += lds[k][t];
+    partials[((size_t)(m.r0 + t) * R + m.sub) * nslots + m.slot] = s;
   }
 }
 
 // ------------------------------------------------------------------ multi-RHS stencil
+// one link load (and, for 12-real links, one third-row reconstruction) serves the NB right-hand
+// sides of the thread's register block
 template <int MU, int DAG, int NB, class Lnk, class S, typename R>
 WHMC_DEV void hop_dir_multi(const Geom& g, const Coords& c, int par, int i, const Lnk& L, const S* in,
                             const bool* act, Spinor<R>* acc) {
@@ -101,83 +177,89 @@ WHMC_DEV void hop_site_multi(const Geom& g, int par, int i, const Lnk& L, const 
   hop_dir_multi<3, DAG, NB>(g, c, par, i, L, in, act, acc);
 }
 
-// plain multi-RHS hop: out_r = H_{par,1-par}^{(dag)} in_r
-template <int DAG, int NB, class Lnk, class S>
-__global__ __launch_bounds__(kBlock) void k_mhop(Geom g, int par, int nrhs, Lnk L, S in0, S out0) {
-  using R = typename S::Real;
-  const int r0 = blockIdx.y * NB;
-  const int i = site_block(g, blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (i >= g.Vh) return;
-  bool act[NB];
+// out_k = H_{par,1-par}^{(DAG)} in_k for the live rhs of the lane's register block
+template <int DAG, int NB, int R, class Lnk, class S, class P>
+WHMC_DEV void mhop_body(const Geom& g, int par, const MLane<NB, R>& m, const Lnk& L, S in0, S out0, const P& live) {
+  using Re = typename S::Real;
+  bool act[NB], any = false;
   S in[NB];
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
-    act[k] = r0 + k < nrhs;
-    in[k] = field(in0, act[k] ? r0 + k : 0);
+    act[k] = live(m.rb + k);
+    any |= act[k];
+    in[k] = field(in0, act[k] ? m.rb + k : 0);
   }
-  Spinor<R> acc[NB];
-  hop_site_multi<DAG, NB>(g, par, i, L, in, act, acc);
+  if (!any) return;
+  Spinor<Re> acc[NB];
+  hop_site_multi<DAG, NB>(g, par, m.i, L, in, act, acc);
 #pragma unroll
   for (int k = 0; k < NB; ++k)
-    if (act[k]) field(out0, r0 + k).store(i, acc[k]);
+    if (act[k]) field(out0, m.rb + k).store(m.i, acc[k]);
 }
 
-WHMC_DEV bool rhs_live(const CGScalars* sc, int r, int nrhs) { return r < nrhs && !(sc[r].done | sc[r].pause); }
-
-template <int NB, class Lnk, class S>
-__global__ __launch_bounds__(kBlock) void k_mcg1(Geom g, int nrhs, Lnk L, S p0, S t0, const CGScalars* sc) {
-  using R = typename S::Real;
-  const int r0 = blockIdx.y * NB;
-  bool act[NB], any = false;
-#pragma unroll
-  for (int k = 0; k < NB; ++k) { act[k] = rhs_live(sc, r0 + k, nrhs); any |= act[k]; }
-  if (!any) return;
-  const int i = site_block(g, blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (i >= g.Vh) return;
-  S in[NB];
-#pragma unroll
-  for (int k = 0; k < NB; ++k) in[k] = field(p0, act[k] ? r0 + k : 0);
-  Spinor<R> acc[NB];
-  hop_site_multi<0, NB>(g, 0, i, L, in, act, acc);
-#pragma unroll
-  for (int k = 0; k < NB; ++k)
-    if (act[k]) field(t0, r0 + k).store(i, acc[k]);
+// plain multi-RHS hop: out_r = H_{par,1-par}^{(dag)} in_r
+template <int DAG, int NB, int R, class Lnk, class S>
+__global__ __launch_bounds__(kBlock) void k_mhop(Geom g, int par, int nrhs, int G, Lnk L, S in0, S out0) {
+  const MLane<NB, R> m = mlane<NB, R>(g, G);
+  if (m.i >= g.Vh) return;
+  mhop_body<DAG>(g, par, m, L, in0, out0, AllRhs{nrhs});
 }
 
-template <int NB, class Lnk, class S>
-__global__ __launch_bounds__(kBlock) void k_mcg2(Geom g, int nrhs, Lnk L, S t0, S p0, S u0, K2 k2, CGScalars* sc,
-                                                 Reduce red) {
-  using R = typename S::Real;
-  const int r0 = blockIdx.y * NB;
-  bool act[NB], any = false;
-#pragma unroll
-  for (int k = 0; k < NB; ++k) { act[k] = rhs_live(sc, r0 + k, nrhs); any |= act[k]; }
-  if (!any) return;
-  const int i = site_block(g, blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+// CG kernel 1: t = H_eo p
+template <int NB, int R, class Lnk, class S, class P>
+__global__ __launch_bounds__(kBlock) void k_mcg1(Geom g, int G, Lnk L, S p0, S t0, P live) {
+  const MLane<NB, R> m = mlane<NB, R>(g, G);
+  if (m.i >= g.Vh) return;
+  mhop_body<0>(g, 0, m, L, p0, t0, live);
+}
+
+// CG kernel 3: v = H^dag_eo u
+template <int NB, int R, class Lnk, class S, class P>
+__global__ __launch_bounds__(kBlock) void k_mcg3(Geom g, int G, Lnk L, S u0, S v0, P live) {
+  const MLane<NB, R> m = mlane<NB, R>(g, G);
+  if (m.i >= g.Vh) return;
+  mhop_body<1>(g, 0, m, L, u0, v0, live);
+}
+
+// CG kernel 2: u = p - kappa^2 H_oe t, |u|^2 = (p, A p)
+template <int NB, int R, class Lnk, class S, class P>
+__global__ __launch_bounds__(kBlock) void k_mcg2(Geom g, int nrhs, int G, Lnk L, S t0, S p0, S u0, K2 k2, P live,
+                                                 Reduce red, int nslots) {
+  using Re = typename S::Real;
+  const MLane<NB, R> m = mlane<NB, R>(g, G);
+  if (!any_live<R * NB>(live, m.r0)) return;   // uniform over the workgroup
   double nrm[NB];
 #pragma unroll
   for (int k = 0; k < NB; ++k) nrm[k] = 0.0;
-  if (i < g.Vh) {
+  if (m.i < g.Vh) {
+    bool act[NB], any = false;
     S in[NB];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) in[k] = field(t0, act[k] ? r0 + k : 0);
-    Spinor<R> acc[NB];
-    hop_site_multi<0, NB>(g, 1, i, L, in, act, acc);
-#pragma unroll
     for (int k = 0; k < NB; ++k) {
-      if (!act[k]) continue;
-      Spinor<R> pv;
-      field(p0, r0 + k).load(i, pv);
-      const R kk = R(k2.v[r0 + k]);
+      act[k] = live(m.rb + k);
+      any |= act[k];
+      in[k] = field(t0, act[k] ? m.rb + k : 0);
+    }
+    if (any) {
+      Spinor<Re> acc[NB];
+      hop_site_multi<0, NB>(g, 1, m.i, L, in, act, acc);
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+      for (int k = 0; k < NB; ++k) {
+        if (!act[k]) continue;
+        const int r = m.rb + k;
+        Spinor<Re> pv;
+        field(p0, r).load(m.i, pv);
+        const Re kk = Re(k2.v[r]);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[k].c[s][c] = pv.c[s][c] - kk * acc[k].c[s][c];
-      field(u0, r0 + k).store(i, acc[k]);
-      nrm[k] = norm2(acc[k]);
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[k].c[s][c] = pv.c[s][c] - kk * acc[k].c[s][c];
+        field(u0, r).store(m.i, acc[k]);
+        nrm[k] = norm2(acc[k]);
+      }
     }
   }
-  block_partials_multi<kBlock, NB>(nrm, red.partials, r0, nrhs);
+  mpartials<NB, R>(nrm, red.partials, m, nrhs, nslots);
 }
 
 __global__ __launch_bounds__(256) void k_mcg2_fin(CGScalars* sc, int nrhs, const double* partials, int nb) {
@@ -194,74 +276,60 @@ __global__ __launch_bounds__(256) void k_mcg2_fin(CGScalars* sc, int nrhs, const
   }
 }
 
-template <int NB, class Lnk, class S>
-__global__ __launch_bounds__(kBlock) void k_mcg3(Geom g, int nrhs, Lnk L, S u0, S v0, const CGScalars* sc) {
-  using R = typename S::Real;
-  const int r0 = blockIdx.y * NB;
-  bool act[NB], any = false;
-#pragma unroll
-  for (int k = 0; k < NB; ++k) { act[k] = rhs_live(sc, r0 + k, nrhs); any |= act[k]; }
-  if (!any) return;
-  const int i = site_block(g, blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (i >= g.Vh) return;
-  S in[NB];
-#pragma unroll
-  for (int k = 0; k < NB; ++k) in[k] = field(u0, act[k] ? r0 + k : 0);
-  Spinor<R> acc[NB];
-  hop_site_multi<1, NB>(g, 0, i, L, in, act, acc);
-#pragma unroll
-  for (int k = 0; k < NB; ++k)
-    if (act[k]) field(v0, r0 + k).store(i, acc[k]);
-}
-
-template <int NB, class Lnk, class S, class SR, bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_mcg4(Geom g, int nrhs, Lnk L, S v0, S u0, S p0, SR rr0, SR x0, K2 k2,
-                                                 CGScalars* sc, Reduce red) {
-  using R = typename S::Real;
+// CG kernel 4: A p = u - kappa^2 H^dag_oe v;  r -= alpha A p,  x += alpha p,  |r|^2
+template <int NB, int R, class Lnk, class S, class SR, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_mcg4(Geom g, int nrhs, int G, Lnk L, S v0, S u0, S p0, SR rr0, SR x0,
+                                                 K2 k2, CGScalars* sc, Reduce red, int nslots) {
+  using Re = typename S::Real;
   using RR = typename SR::Real;
-  const int r0 = blockIdx.y * NB;
-  bool act[NB], any = false;
-#pragma unroll
-  for (int k = 0; k < NB; ++k) { act[k] = rhs_live(sc, r0 + k, nrhs); any |= act[k]; }
-  if (!any) return;
-  const int i = site_block(g, blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const MLane<NB, R> m = mlane<NB, R>(g, G);
+  const ByScalars live{sc, nrhs};
+  if (!any_live<R * NB>(live, m.r0)) return;   // uniform over the workgroup
   double nrm[NB];
 #pragma unroll
   for (int k = 0; k < NB; ++k) nrm[k] = 0.0;
-  if (i < g.Vh) {
+  if (m.i < g.Vh) {
+    const int i = m.i;
+    bool act[NB], any = false;
     S in[NB];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) in[k] = field(v0, act[k] ? r0 + k : 0);
-    Spinor<R> acc[NB];
-    hop_site_multi<1, NB>(g, 1, i, L, in, act, acc);
-#pragma unroll
     for (int k = 0; k < NB; ++k) {
-      if (!act[k]) continue;
-      const int r = r0 + k;
-      const RR alpha = RR(sc[r].alpha);
-      const R kk = R(k2.v[r]);
-      Spinor<R> uv, pv;
-      Spinor<RR> rv, xv;
-      field(u0, r).load(i, uv);
-      field(p0, r).load(i, pv);
-      field(rr0, r).load(i, rv);
-      field(x0, r).load(i, xv);
+      act[k] = live(m.rb + k);
+      any |= act[k];
+      in[k] = field(v0, act[k] ? m.rb + k : 0);
+    }
+    if (any) {
+      Spinor<Re> acc[NB];
+      hop_site_multi<1, NB>(g, 1, i, L, in, act, acc);
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+      for (int k = 0; k < NB; ++k) {
+        if (!act[k]) continue;
+        const int r = m.rb + k;
+        const RR alpha = RR(sc[r].alpha);
+        const Re kk = Re(k2.v[r]);
+        Spinor<Re> uv, pv;
+        Spinor<RR> rv, xv;
+        field(u0, r).load(i, uv);
+        field(p0, r).load(i, pv);
+        field(rr0, r).load(i, rv);
+        field(x0, r).load(i, xv);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          cplx<R> ap = uv.c[s][c] - kk * acc[k].c[s][c];
-          rv.c[s][c].re -= alpha * RR(ap.re);
-          rv.c[s][c].im -= alpha * RR(ap.im);
-          xv.c[s][c].re += alpha * RR(pv.c[s][c].re);
-          xv.c[s][c].im += alpha * RR(pv.c[s][c].im);
-        }
-      field(rr0, r).store(i, rv);
-      field(x0, r).store(i, xv);
-      nrm[k] = norm2(rv);
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            cplx<Re> ap = uv.c[s][c] - kk * acc[k].c[s][c];
+            rv.c[s][c].re -= alpha * RR(ap.re);
+            rv.c[s][c].im -= alpha * RR(ap.im);
+            xv.c[s][c].re += alpha * RR(pv.c[s][c].re);
+            xv.c[s][c].im += alpha * RR(pv.c[s][c].im);
+          }
+        field(rr0, r).store(i, rv);
+        field(x0, r).store(i, xv);
+        nrm[k] = norm2(rv);
+      }
     }
   }
-  block_partials_multi<kBlock, NB>(nrm, red.partials, r0, nrhs);
+  mpartials<NB, R>(nrm, red.partials, m, nrhs, nslots);
 }
 
 template <bool MIXED>
@@ -286,6 +354,40 @@ __global__ __launch_bounds__(256) void k_mcg4_fin(CGScalars* sc, int nrhs, const
   } else {
     if (rr_new <= q.stop_rr) q.done = 1;
   }
+}
+
+// FP64 residual of the host-chosen right-hand sides, last hop of M^dag M fused:
+// r_r = b_r - (u_r - kappa_r^2 H^dag_oe v_r), |r_r|^2 to the partial sums
+template <int R, class Lnk>
+__global__ __launch_bounds__(kBlock) void k_mres(Geom g, int nrhs, int G, Lnk L, SpinorF64 v0, SpinorF64 u0,
+                                                 SpinorF64 b0, SpinorF64 r0, K2 k2, BySet live, Reduce red,
+                                                 int nslots) {
+  const MLane<1, R> m = mlane<1, R>(g, G);
+  if (!any_live<R>(live, m.r0)) return;   // uniform over the workgroup
+  double nrm = 0.0;
+  if (m.i < g.Vh && live(m.rb)) {
+    const int r = m.rb, i = m.i;
+    Spinor<double> acc, uv, bv;
+    hop_site<1>(g, 1, i, L, field(v0, r), acc);
+    field(u0, r).load(i, uv);
+    field(b0, r).load(i, bv);
+    const double kk = k2.v[r];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc.c[s][c] = bv.c[s][c] - (uv.c[s][c] - kk * acc.c[s][c]);
+    field(r0, r).store(i, acc);
+    nrm = norm2(acc);
+  }
+  mpartials<1, R>(&nrm, red.partials, m, nrhs, nslots);
+}
+
+// pass 2 of k_mres: out[r] = |r_r|^2 for the chosen right-hand sides
+__global__ __launch_bounds__(256) void k_mres_fin(BySet live, const double* partials, int nb, double* out) {
+  const int r = blockIdx.x;
+  if (!live(r)) return;
+  const double rr = sum_partials<256>(partials + (size_t)r * nb, nb);
+  if (threadIdx.x == 0) out[r] = rr;
 }
 
 template <class S, class SR>
@@ -317,24 +419,62 @@ static SpinorF32 h32(void* p, int Vh) { return SpinorF32{(float4*)p, Vh}; }
 static SpinorF16 h16(void* p, int Vh) { return SpinorF16{(uint4*)p, (float*)((uint4*)p + (size_t)3 * Vh), Vh}; }
 static size_t field_bytes(int prec, int Vh) { return (size_t)Vh * (prec == WHMC_F64 ? 192 : prec == WHMC_F32 ? 96 : 52); }
 
-template <int NB, class Lnk, class S>
-static void launch_mhop(whmc_ctx* c, int par, int dag, int nrhs, const Lnk& L, S in, S out) {
-  dim3 grid(c->num_blocks(), (nrhs + NB - 1) / NB), block(kBlock);
-  if (dag) hipLaunchKernelGGL((k_mhop<1, NB, Lnk, S>), grid, block, 0, c->stream, c->g, par, nrhs, L, in, out);
-  else hipLaunchKernelGGL((k_mhop<0, NB, Lnk, S>), grid, block, 0, c->stream, c->g, par, nrhs, L, in, out);
+// Blocking of the multi-RHS kernels: NB right-hand sides per thread (register block) and R lanes
+// per site sharing each link load.  FP64 keeps NB = 1 (its single-rhs hop already fills the
+// register file); the low-precision formats, whose cost per site is dominated by link decoding,
+// also block in registers.
+struct Blocking {
+  int nb, lanes;
+};
+
+template <class Lnk>
+static constexpr bool is_f64_links() { return std::is_same<typename Lnk::Real, double>::value; }
+
+// call f(integral_constant<NB>, integral_constant<R>) for an allowed blocking of this link format
+template <class Lnk, class F>
+static whmc_status with_blocking(Blocking b, F&& f) {
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I4 = std::integral_constant<int, 4>;
+  if constexpr (is_f64_links<Lnk>()) {
+    if (b.nb == 1 && b.lanes == 1) return f(I1{}, I1{});
+    if (b.nb == 1 && b.lanes == 2) return f(I1{}, I2{});
+    if (b.nb == 1 && b.lanes == 4) return f(I1{}, I4{});
+  } else {
+    if (b.nb == 1 && b.lanes == 1) return f(I1{}, I1{});
+    if (b.nb == 1 && b.lanes == 2) return f(I1{}, I2{});
+    if (b.nb == 2 && b.lanes == 1) return f(I2{}, I1{});
+    if (b.nb == 2 && b.lanes == 2) return f(I2{}, I2{});
+    if (b.nb == 4 && b.lanes == 1) return f(I4{}, I1{});
+    if (b.nb == 4 && b.lanes == 2) return f(I4{}, I2{});
+  }
+  set_error("multi-RHS blocking: FP64 takes rhs_block 1 with rhs_lanes 1, 2 or 4; FP32 / FP16 take rhs_block 1, 2 "
+            "or 4 with rhs_lanes 1 or 2");
+  return WHMC_EARG;
 }
 
-template <class Lnk, class S>
-static whmc_status mhop_nb(whmc_ctx* c, int nb, int par, int dag, int nrhs, const Lnk& L, S in, S out) {
-  switch (nb) {
-    case 1: launch_mhop<1>(c, par, dag, nrhs, L, in, out); break;
-    case 2: launch_mhop<2>(c, par, dag, nrhs, L, in, out); break;
-    case 3: launch_mhop<3>(c, par, dag, nrhs, L, in, out); break;
-    case 4: launch_mhop<4>(c, par, dag, nrhs, L, in, out); break;
-    default: set_error("rhs_block must be 1..4"); return WHMC_EARG;
+// the blockings the autotuner tries for a precision, nrhs right-hand sides
+static std::vector<Blocking> candidates(int prec, int nrhs) {
+  std::vector<Blocking> out;
+  const int nbs[3] = {1, 2, 4}, ls[3] = {1, 2, 4};
+  for (int nb : nbs) {
+    if (prec == WHMC_F64 && nb > 1) break;
+    for (int l : ls) {
+      if (prec != WHMC_F64 && l > 2) break;
+      const int group = nb * l;
+      if (group > 1 && group / 2 >= nrhs) continue;   // wider than needed: idle lanes or registers
+      out.push_back({nb, l});
+    }
   }
-  WHMC_HIP(hipGetLastError());
-  return WHMC_OK;
+  return out;
+}
+
+template <int NB, int R, class Lnk, class S>
+static void launch_mhop(whmc_ctx* c, int par, int dag, int nrhs, const Lnk& L, S in, S out) {
+  const int G = (nrhs + R * NB - 1) / (R * NB);
+  const dim3 grid(c->stencil_blocks() * G * R), block(kBlock);
+  if (dag) hipLaunchKernelGGL((k_mhop<1, NB, R, Lnk, S>), grid, block, 0, c->stream, c->g, par, nrhs, G, L, in, out);
+  else hipLaunchKernelGGL((k_mhop<0, NB, R, Lnk, S>), grid, block, 0, c->stream, c->g, par, nrhs, G, L, in, out);
 }
 
 // dispatch on precision / link format / cache policy; f(L, S-maker) is called with the typed link
@@ -364,18 +504,26 @@ static whmc_status with_format(whmc_ctx* c, int prec, int links, F&& f) {
   return WHMC_EUNSUP;
 }
 
-whmc_status mhop(whmc_ctx* c, int prec, int links, int par, int dag, int nrhs, int nb, void* out, const void* in) {
-  return with_format(c, prec, links, [&](auto L, auto mk) {
-    return mhop_nb(c, nb, par, dag, nrhs, L, mk((void*)in, c->Vh), mk(out, c->Vh));
-  });
+static whmc_status mhop(whmc_ctx* c, int prec, int links, int par, int dag, int nrhs, Blocking b, void* out,
+                        const void* in) {
+  WHMC_TRY(with_format(c, prec, links, [&](auto L, auto mk) {
+    return with_blocking<decltype(L)>(b, [&](auto nb, auto lanes) {
+      launch_mhop<decltype(nb)::value, decltype(lanes)::value>(c, par, dag, nrhs, L, mk((void*)in, c->Vh),
+                                                                mk(out, c->Vh));
+      return WHMC_OK;
+    });
+  }));
+  WHMC_HIP(hipGetLastError());
+  return WHMC_OK;
 }
 
-// ---- autotuner: time the multi-RHS hop for every register block and keep the fastest
-whmc_status autotune_rhs_block(whmc_ctx* c, int prec, int links, int nrhs, int* best_nb, double* best_us) {
+// ---- autotuner: time the multi-RHS hop for every candidate blocking and keep the fastest
+static whmc_status autotune_blocking(whmc_ctx* c, int prec, int links, int nrhs, Blocking* best, double* best_us) {
   const std::string key = std::to_string(prec) + "/" + std::to_string(links) + "/" + std::to_string(nrhs);
   auto it = c->tuned.find(key);
   if (it != c->tuned.end()) {
-    *best_nb = it->second.first;
+    best->nb = it->second.first / 16;
+    best->lanes = it->second.first % 16;
     if (best_us) *best_us = it->second.second;
     return WHMC_OK;
   }
@@ -387,13 +535,12 @@ whmc_status autotune_rhs_block(whmc_ctx* c, int prec, int links, int nrhs, int* 
   hipEvent_t e0, e1;
   WHMC_HIP(hipEventCreate(&e0));
   WHMC_HIP(hipEventCreate(&e1));
-  int bnb = 1;
+  Blocking bb{1, 1};
   double bt = 1e30;
-  const int maxnb = nrhs < 4 ? nrhs : 4;
-  for (int nb = 1; nb <= maxnb; ++nb) {
-    WHMC_TRY(mhop(c, prec, links, 0, 0, nrhs, nb, out, in));   // warm-up
+  for (const Blocking& b : candidates(prec, nrhs)) {
+    WHMC_TRY(mhop(c, prec, links, 0, 0, nrhs, b, out, in));   // warm-up
     WHMC_HIP(hipEventRecord(e0, c->stream));
-    for (int rep = 0; rep < 3; ++rep) WHMC_TRY(mhop(c, prec, links, 0, 0, nrhs, nb, out, in));
+    for (int rep = 0; rep < 3; ++rep) WHMC_TRY(mhop(c, prec, links, 0, 0, nrhs, b, out, in));
     WHMC_HIP(hipEventRecord(e1, c->stream));
     WHMC_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -401,14 +548,22 @@ whmc_status autotune_rhs_block(whmc_ctx* c, int prec, int links, int nrhs, int* 
     const double us = ms * 1e3 / 3.0;
     if (us < bt) {
       bt = us;
-      bnb = nb;
+      bb = b;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  c->tuned[key] = {bnb, bt};
-  *best_nb = bnb;
+  c->tuned[key] = {bb.nb * 16 + bb.lanes, bt};
+  *best = bb;
   if (best_us) *best_us = bt;
+  return WHMC_OK;
+}
+
+// the blocking a call asks for: both 0 = autotuned, else the given values (0 read as 1)
+static whmc_status resolve_blocking(whmc_ctx* c, int prec, int links, int nrhs, int nb, int lanes, Blocking* b) {
+  if (nb <= 0 && lanes <= 0) return autotune_blocking(c, prec, links, nrhs, b, nullptr);
+  b->nb = nb > 0 ? nb : 1;
+  b->lanes = lanes > 0 ? lanes : 1;
   return WHMC_OK;
 }
 
@@ -508,43 +663,59 @@ __global__ __launch_bounds__(kBlock) void k_mrel_p(int Vh, S p, SR r, const doub
   p.store(i, pv);
 }
 
-template <int NB, bool MIXED, class Lnk, class S, class SR>
+template <int NB, int R, bool MIXED, class Lnk, class S, class SR>
 static void enqueue_multi(whmc_ctx* c, int nrhs, const Lnk& L, S p, S t, S u, S v, SR r, SR x, const K2& k2, int n) {
-  const dim3 grid(c->num_blocks(), (nrhs + NB - 1) / NB), block(kBlock), grid5(c->num_blocks(), nrhs);
+  const int G = (nrhs + R * NB - 1) / (R * NB), ns = c->stencil_blocks();
+  const dim3 grid(ns * G * R), block(kBlock), grid5(c->num_blocks(), nrhs);
+  const ByScalars live{c->scal, nrhs};
   for (int it = 0; it < n; ++it) {
-    hipLaunchKernelGGL((k_mcg1<NB, Lnk, S>), grid, block, 0, c->stream, c->g, nrhs, L, p, t, c->scal);
-    hipLaunchKernelGGL((k_mcg2<NB, Lnk, S>), grid, block, 0, c->stream, c->g, nrhs, L, t, p, u, k2, c->scal, c->red);
-    hipLaunchKernelGGL(k_mcg2_fin, dim3(nrhs), dim3(256), 0, c->stream, c->scal, nrhs, c->red.partials, (int)grid.x);
-    hipLaunchKernelGGL((k_mcg3<NB, Lnk, S>), grid, block, 0, c->stream, c->g, nrhs, L, u, v, c->scal);
-    hipLaunchKernelGGL((k_mcg4<NB, Lnk, S, SR, MIXED>), grid, block, 0, c->stream, c->g, nrhs, L, v, u, p, r, x, k2,
-                       c->scal, c->red);
+    hipLaunchKernelGGL((k_mcg1<NB, R, Lnk, S, ByScalars>), grid, block, 0, c->stream, c->g, G, L, p, t, live);
+    hipLaunchKernelGGL((k_mcg2<NB, R, Lnk, S, ByScalars>), grid, block, 0, c->stream, c->g, nrhs, G, L, t, p, u, k2,
+                       live, c->red, ns);
+    hipLaunchKernelGGL(k_mcg2_fin, dim3(nrhs), dim3(256), 0, c->stream, c->scal, nrhs, c->red.partials, ns * R);
+    hipLaunchKernelGGL((k_mcg3<NB, R, Lnk, S, ByScalars>), grid, block, 0, c->stream, c->g, G, L, u, v, live);
+    hipLaunchKernelGGL((k_mcg4<NB, R, Lnk, S, SR, MIXED>), grid, block, 0, c->stream, c->g, nrhs, G, L, v, u, p, r, x,
+                       k2, c->scal, c->red, ns);
     hipLaunchKernelGGL(k_mcg4_fin<MIXED>, dim3(nrhs), dim3(256), 0, c->stream, c->scal, nrhs, c->red.partials,
-                       (int)grid.x);
+                       ns * R);
     hipLaunchKernelGGL((k_mcg5<S, SR>), grid5, block, 0, c->stream, c->Vh, nrhs, p, r, c->scal);
   }
 }
 
-template <bool MIXED, class Lnk, class S, class SR>
-static whmc_status enqueue_multi_nb(whmc_ctx* c, int nb, int nrhs, const Lnk& L, S p, S t, S u, S v, SR r, SR x,
-                                    const K2& k2, int n) {
-  switch (nb) {
-    case 1: enqueue_multi<1, MIXED>(c, nrhs, L, p, t, u, v, r, x, k2, n); break;
-    case 2: enqueue_multi<2, MIXED>(c, nrhs, L, p, t, u, v, r, x, k2, n); break;
-    case 3: enqueue_multi<3, MIXED>(c, nrhs, L, p, t, u, v, r, x, k2, n); break;
-    default: enqueue_multi<4, MIXED>(c, nrhs, L, p, t, u, v, r, x, k2, n); break;
-  }
-  WHMC_HIP(hipGetLastError());
-  return WHMC_OK;
+// r_r = b_r - M_oo(kappa_r)^dag M_oo(kappa_r) x_r for every rhs r in mask, FP64 with 18-real links,
+// through the multi-RHS kernels (one pass over the links serves all of them); |r_r|^2 lands in
+// rr_dev[r].  t, u, v, r64 are FP64 scratch of nrhs half fields each.
+template <int R, class Lnk>
+static void enqueue_residual(whmc_ctx* c, unsigned mask, int nrhs, const Lnk& L, SpinorF64 x, SpinorF64 b,
+                             const K2& k2, SpinorF64 t, SpinorF64 u, SpinorF64 v, SpinorF64 r64, double* rr_dev) {
+  const int G = (nrhs + R - 1) / R, ns = c->stencil_blocks();
+  const dim3 grid(ns * G * R), block(kBlock);
+  const BySet live{mask, nrhs};
+  hipLaunchKernelGGL((k_mcg1<1, R, Lnk, SpinorF64, BySet>), grid, block, 0, c->stream, c->g, G, L, x, t, live);
+  hipLaunchKernelGGL((k_mcg2<1, R, Lnk, SpinorF64, BySet>), grid, block, 0, c->stream, c->g, nrhs, G, L, t, x, u, k2,
+                     live, c->red, ns);
+  hipLaunchKernelGGL((k_mcg3<1, R, Lnk, SpinorF64, BySet>), grid, block, 0, c->stream, c->g, G, L, u, v, live);
+  hipLaunchKernelGGL((k_mres<R, Lnk>), grid, block, 0, c->stream, c->g, nrhs, G, L, v, u, b, r64, k2, live, c->red,
+                     ns);
+  hipLaunchKernelGGL(k_mres_fin, dim3(nrhs), dim3(256), 0, c->stream, live, c->red.partials, ns * R, rr_dev);
 }
 
-static whmc_status true_residual_r(whmc_ctx* c, double* r_out, const double* x, const double* b, double kappa,
-                                   double* te, double* to, double bb, double* rel) {
-  WHMC_TRY(apply_MdagM_f64(c, r_out, x, kappa, te, to));
-  WHMC_TRY(axpby_f64(c, r_out, 1.0, b, -1.0, 1));
-  double rr;
-  WHMC_TRY(norm2_f64(c, r_out, 1, c->red.result + 2));
-  WHMC_TRY(read_scalar(c, c->red.result + 2, &rr));
-  *rel = std::sqrt(rr / bb);
+static whmc_status residual_multi(whmc_ctx* c, unsigned mask, int nrhs, const double* x, const double* b,
+                                  const K2& k2, void* t, void* u, void* v, void* r64, double* rr_dev) {
+  Blocking bk;
+  WHMC_TRY(autotune_blocking(c, WHMC_F64, WHMC_L18, nrhs, &bk, nullptr));
+  const int Vh = c->Vh;
+  auto run = [&](auto L) {
+    return with_blocking<decltype(L)>(bk, [&](auto nb, auto lanes) {
+      (void)nb;
+      enqueue_residual<decltype(lanes)::value>(c, mask, nrhs, L, h64((void*)x, Vh), h64((void*)b, Vh), k2, h64(t, Vh),
+                                               h64(u, Vh), h64(v, Vh), h64(r64, Vh), rr_dev);
+      return WHMC_OK;
+    });
+  };
+  if (c->stream_links(WHMC_F64, WHMC_L18)) WHMC_TRY(run(LinkF64_18T<true>{c->U18, Vh}));
+  else WHMC_TRY(run(LinkF64_18T<false>{c->U18, Vh}));
+  WHMC_HIP(hipGetLastError());
   return WHMC_OK;
 }
 
@@ -571,19 +742,26 @@ whmc_status cg_solve_multi(whmc_ctx* c, double* x, const double* b, const double
   const size_t sb = field_bytes(prec, Vh);
   const int rprec = mixed ? WHMC_F32 : WHMC_F64;
   const size_t rb = field_bytes(rprec, Vh);
-  int nb = prm->rhs_block;
-  if (nb <= 0) WHMC_TRY(autotune_rhs_block(c, prec, links, nrhs, &nb, nullptr));
-  WHMC_CHECK(nb >= 1 && nb <= 4, WHMC_EARG, "rhs_block must be 0 (autotune) or 1..4");
-  void *p, *t, *u, *v, *rs, *xs, *r64, *te, *to;
+  Blocking bk;
+  WHMC_TRY(resolve_blocking(c, prec, links, nrhs, prm->rhs_block, prm->rhs_lanes, &bk));
+  void *p, *t, *u, *v, *rs, *xs, *r64, *ft, *fu, *fv;
   WHMC_TRY(workspace(c, "m_p", sb * nrhs, &p));
   WHMC_TRY(workspace(c, "m_t", sb * nrhs, &t));
   WHMC_TRY(workspace(c, "m_u", sb * nrhs, &u));
   WHMC_TRY(workspace(c, "m_v", sb * nrhs, &v));
   WHMC_TRY(workspace(c, "m_r", rb * nrhs, &rs));
   WHMC_TRY(workspace(c, "m_x", rb * nrhs, &xs));
-  WHMC_TRY(workspace(c, "cg_r", hb, &r64));
-  WHMC_TRY(workspace(c, "cg_te", hb, &te));
-  WHMC_TRY(workspace(c, "cg_to", hb, &to));
+  WHMC_TRY(workspace(c, "m_r64", hb * nrhs, &r64));
+  // FP64 scratch of the batched true residuals (the iteration's own fields when those are FP64)
+  if (mixed) {
+    WHMC_TRY(workspace(c, "m_ft", hb * nrhs, &ft));
+    WHMC_TRY(workspace(c, "m_fu", hb * nrhs, &fu));
+    WHMC_TRY(workspace(c, "m_fv", hb * nrhs, &fv));
+  } else {
+    ft = t, fu = u, fv = v;
+  }
+  double* rr_dev = c->red.result + 32;
+  double* rr_host = c->host_pinned + 32;
   std::vector<double> bb(nrhs);
   for (int r = 0; r < nrhs; ++r) WHMC_TRY(norm2_f64(c, b + (size_t)r * 24 * Vh, 1, c->red.result + 16 + r));
   WHMC_HIP(hipMemcpyAsync(c->host_pinned + 16, c->red.result + 16, nrhs * sizeof(double), hipMemcpyDeviceToHost,
@@ -614,38 +792,49 @@ whmc_status cg_solve_multi(whmc_ctx* c, double* x, const double* b, const double
     int max_iter_seen = 0;
     while (true) {
       WHMC_TRY(with_format(c, prec, links, [&](auto L, auto mk) {
-        if (mixed)
-          return enqueue_multi_nb<true>(c, nb, nrhs, L, mk(p, Vh), mk(t, Vh), mk(u, Vh), mk(v, Vh), h32(rs, Vh),
-                                        h32(xs, Vh), k2, check);
-        return enqueue_multi_nb<false>(c, nb, nrhs, L, mk(p, Vh), mk(t, Vh), mk(u, Vh), mk(v, Vh), h64(rs, Vh),
-                                       h64(xs, Vh), k2, check);
+        return with_blocking<decltype(L)>(bk, [&](auto nbc, auto lanes) {
+          constexpr int NB = decltype(nbc)::value, R = decltype(lanes)::value;
+          // FP64 links run the plain FP64 CG, low-precision links the mixed one
+          if constexpr (is_f64_links<decltype(L)>())
+            enqueue_multi<NB, R, false>(c, nrhs, L, mk(p, Vh), mk(t, Vh), mk(u, Vh), mk(v, Vh), h64(rs, Vh),
+                                        h64(xs, Vh), k2, check);
+          else
+            enqueue_multi<NB, R, true>(c, nrhs, L, mk(p, Vh), mk(t, Vh), mk(u, Vh), mk(v, Vh), h32(rs, Vh),
+                                       h32(xs, Vh), k2, check);
+          return WHMC_OK;
+        });
       }));
+      WHMC_HIP(hipGetLastError());
       WHMC_HIP(hipMemcpyAsync(hs, c->scal, nrhs * sizeof(CGScalars), hipMemcpyDeviceToHost, c->stream));
       WHMC_HIP(hipStreamSynchronize(c->stream));
       bool live = false;
       max_iter_seen = 0;
       for (int r = 0; r < nrhs; ++r) max_iter_seen = std::max(max_iter_seen, hs[r].iter);
+      unsigned paused = 0;
       for (int r = 0; r < nrhs; ++r) {
-        const CGScalars q = hs[r];
-        if (mixed && q.pause && !q.done) {
-          // reliable update of rhs r in FP64
-          double* xr = x + (size_t)r * 24 * Vh;
-          const double* br = b + (size_t)r * 24 * Vh;
-          char* xsr = (char*)xs + rb * r;
+        if (mixed && hs[r].pause && !hs[r].done) paused |= 1u << r;
+        else if (!hs[r].done) live = true;
+      }
+      if (paused) {
+        // reliable updates of the paused right-hand sides, batched: x += x_s in FP64, then
+        // r = b - A x and |r|^2 for all of them in one multi-RHS FP64 pass
+        for (int r = 0; r < nrhs; ++r)
+          if ((paused >> r) & 1u)
+            hipLaunchKernelGGL((k_maccum_x<SpinorF32>), dim3((Vh + 255) / 256), dim3(256), 0, c->stream, Vh,
+                               (double2*)(x + (size_t)r * 24 * Vh), h32((char*)xs + rb * r, Vh));
+        WHMC_HIP(hipGetLastError());
+        WHMC_TRY(residual_multi(c, paused, nrhs, x, b, k2, ft, fu, fv, r64, rr_dev));
+        WHMC_HIP(hipMemcpyAsync(rr_host, rr_dev, nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        WHMC_HIP(hipStreamSynchronize(c->stream));
+        for (int r = 0; r < nrhs; ++r) {
+          if (!((paused >> r) & 1u)) continue;
           char* rsr = (char*)rs + rb * r;
           char* pr = (char*)p + sb * r;
-          hipLaunchKernelGGL((k_maccum_x<SpinorF32>), dim3((Vh + 255) / 256), dim3(256), 0, c->stream, Vh,
-                             (double2*)xr, h32(xsr, Vh));
-          WHMC_HIP(hipGetLastError());
-          double rel;
-          WHMC_TRY(true_residual_r(c, (double*)r64, xr, br, kappas[r], (double*)te, (double*)to, bb[r], &rel));
+          const double rel = std::sqrt(rr_host[r] / bb[r]);
           rel_updates[r] += 1;
           const int ok = rel <= prm->tol;
-          if (!ok) {
-            WHMC_TRY(convert_spinor(c, rsr, WHMC_F32, r64, WHMC_F64, 1));
-            WHMC_TRY(norm2_f64(c, (double*)r64, 1, c->red.result + 5));
-          }
-          hipLaunchKernelGGL(k_mresume, dim3(1), dim3(64), 0, c->stream, c->scal, r, c->red.result + 5, ok);
+          if (!ok) WHMC_TRY(convert_spinor(c, rsr, WHMC_F32, (char*)r64 + hb * r, WHMC_F64, 1));
+          hipLaunchKernelGGL(k_mresume, dim3(1), dim3(64), 0, c->stream, c->scal, r, rr_dev + r, ok);
           if (!ok) {
             const dim3 gr(c->num_blocks());
             WHMC_TRY(with_format(c, prec, links, [&](auto L, auto mk) {
@@ -661,8 +850,6 @@ whmc_status cg_solve_multi(whmc_ctx* c, double* x, const double* b, const double
           WHMC_HIP(hipGetLastError());
           conv[r] = ok;
           if (!ok) live = true;
-        } else if (!q.done) {
-          live = true;
         }
       }
       if (!live || max_iter_seen >= prm->maxiter) break;
@@ -671,9 +858,9 @@ whmc_status cg_solve_multi(whmc_ctx* c, double* x, const double* b, const double
     WHMC_HIP(hipMemcpyAsync(hs, c->scal, nrhs * sizeof(CGScalars), hipMemcpyDeviceToHost, c->stream));
     WHMC_HIP(hipStreamSynchronize(c->stream));
     all = true;
+    unsigned nonzero = 0;
     for (int r = 0; r < nrhs; ++r) {
       double* xr = x + (size_t)r * 24 * Vh;
-      const double* br = b + (size_t)r * 24 * Vh;
       if (mixed) {
         if (!conv[r]) {
           hipLaunchKernelGGL((k_maccum_x<SpinorF32>), dim3((Vh + 255) / 256), dim3(256), 0, c->stream, Vh,
@@ -683,17 +870,22 @@ whmc_status cg_solve_multi(whmc_ctx* c, double* x, const double* b, const double
       } else {
         WHMC_HIP(hipMemcpyAsync(xr, (char*)xs + rb * r, hb, hipMemcpyDeviceToDevice, c->stream));
       }
-      double rel = 0.0;
-      if (bb[r] != 0.0)
-        WHMC_TRY(true_residual_r(c, (double*)r64, xr, br, kappas[r], (double*)te, (double*)to, bb[r], &rel));
+      if (bb[r] != 0.0) nonzero |= 1u << r;
+    }
+    if (nonzero) {
+      WHMC_TRY(residual_multi(c, nonzero, nrhs, x, b, k2, ft, fu, fv, r64, rr_dev));
+      WHMC_HIP(hipMemcpyAsync(rr_host, rr_dev, nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      WHMC_HIP(hipStreamSynchronize(c->stream));
+    }
+    for (int r = 0; r < nrhs; ++r) {
+      const double rel = ((nonzero >> r) & 1u) ? std::sqrt(rr_host[r] / bb[r]) : 0.0;
       rel_final[r] = rel;
       const bool ok = rel <= prm->tol;
       if (!ok && !mixed) {
-        // restart this rhs from its true residual (r64 = b - A x): r = p = r64, x continues
-        WHMC_HIP(hipMemcpyAsync((char*)rs + rb * r, r64, hb, hipMemcpyDeviceToDevice, c->stream));
-        WHMC_HIP(hipMemcpyAsync((char*)p + sb * r, r64, hb, hipMemcpyDeviceToDevice, c->stream));
-        WHMC_TRY(norm2_f64(c, (double*)r64, 1, c->red.result + 5));
-        hipLaunchKernelGGL(k_mrestart, dim3(1), dim3(64), 0, c->stream, c->scal, r, c->red.result + 5,
+        // restart this rhs from its true residual b - A x: r = p = that residual, x continues
+        WHMC_HIP(hipMemcpyAsync((char*)rs + rb * r, (char*)r64 + hb * r, hb, hipMemcpyDeviceToDevice, c->stream));
+        WHMC_HIP(hipMemcpyAsync((char*)p + sb * r, (char*)r64 + hb * r, hb, hipMemcpyDeviceToDevice, c->stream));
+        hipLaunchKernelGGL(k_mrestart, dim3(1), dim3(64), 0, c->stream, c->scal, r, rr_dev + r,
                            prm->tol * prm->tol * bb[r]);
         WHMC_HIP(hipGetLastError());
       }
@@ -722,17 +914,23 @@ whmc_status cg_solve_multi(whmc_ctx* c, double* x, const double* b, const double
 using namespace whmc;
 
 extern "C" whmc_status whmc_apply_H_multi(whmc_ctx* c, void* out, const void* in, int out_parity, int dagger,
-                                          int prec, int links, int nrhs, int rhs_block) {
+                                          int prec, int links, int nrhs, int rhs_block, int rhs_lanes) {
   WHMC_CHECK(c && out && in && out != in, WHMC_EARG, "whmc_apply_H_multi: bad pointers");
   WHMC_CHECK(out_parity == 0 || out_parity == 1, WHMC_EARG, "whmc_apply_H_multi: out_parity must be 0 or 1");
   WHMC_CHECK(nrhs >= 1 && nrhs <= kMaxRhs, WHMC_EARG, "whmc_apply_H_multi: nrhs must be in [1, 16]");
-  int nb = rhs_block;
-  if (nb <= 0) WHMC_TRY(autotune_rhs_block(c, prec, links, nrhs, &nb, nullptr));
-  return mhop(c, prec, links, out_parity, dagger ? 1 : 0, nrhs, nb, out, in);
+  Blocking b;
+  WHMC_TRY(resolve_blocking(c, prec, links, nrhs, rhs_block, rhs_lanes, &b));
+  return mhop(c, prec, links, out_parity, dagger ? 1 : 0, nrhs, b, out, in);
 }
 
-extern "C" whmc_status whmc_autotune(whmc_ctx* c, int prec, int links, int nrhs, int* rhs_block, double* us) {
-  WHMC_CHECK(c && rhs_block, WHMC_EARG, "whmc_autotune: null argument");
+extern "C" whmc_status whmc_autotune(whmc_ctx* c, int prec, int links, int nrhs, int* rhs_block, int* rhs_lanes,
+                                     double* us) {
+  WHMC_CHECK(c && rhs_block && rhs_lanes, WHMC_EARG, "whmc_autotune: null argument");
   WHMC_CHECK(nrhs >= 1 && nrhs <= kMaxRhs, WHMC_EARG, "whmc_autotune: nrhs must be in [1, 16]");
-  return autotune_rhs_block(c, prec, links, nrhs, rhs_block, us);
+  Blocking b;
+  WHMC_TRY(autotune_blocking(c, prec, links, nrhs, &b, us));
+  *rhs_block = b.nb;
+  *rhs_lanes = b.lanes;
+  return WHMC_OK;
 }
+

@@ -33,7 +33,7 @@ class WhmcError(RuntimeError):
 class CGParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("prec", ctypes.c_int),
                 ("links", ctypes.c_int), ("delta", ctypes.c_double), ("check_every", ctypes.c_int),
-                ("rhs_block", ctypes.c_int)]
+                ("rhs_block", ctypes.c_int), ("rhs_lanes", ctypes.c_int)]
 
 
 class CGStats(ctypes.Structure):
@@ -63,8 +63,8 @@ class TrajResult(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-def cg_params(tol=1e-10, maxiter=10000, prec=F64, links=L18, delta=0.1, check_every=8, rhs_block=0):
-    return CGParams(tol, maxiter, prec, links, delta, check_every, rhs_block)
+def cg_params(tol=1e-10, maxiter=10000, prec=F64, links=L18, delta=0.1, check_every=8, rhs_block=0, rhs_lanes=0):
+    return CGParams(tol, maxiter, prec, links, delta, check_every, rhs_block, rhs_lanes)
 
 
 _lib = None
@@ -86,9 +86,9 @@ _SIGS = {
     "whmc_apply_H": ([_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "whmc_apply_Moo": ([_P, _P, _P, ctypes.c_double, ctypes.c_int], ctypes.c_int),
     "whmc_apply_H_multi": ([_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                            ctypes.c_int], ctypes.c_int),
+                            ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "whmc_autotune": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
-                       ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "whmc_apply_MdagM": ([_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int], ctypes.c_int),
     "whmc_cg_solve": ([_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.POINTER(CGParams),
                        ctypes.POINTER(CGStats)], ctypes.c_int),
@@ -247,17 +247,19 @@ class Context:
         _check(lib().whmc_apply_H(self._h, _ptr(out), _ptr(inp), out_parity, int(dagger), prec, links))
         return out
 
-    def apply_H_multi(self, inp, out_parity, nrhs, dagger=False, prec=F64, links=L18, rhs_block=0, out=None):
+    def apply_H_multi(self, inp, out_parity, nrhs, dagger=False, prec=F64, links=L18, rhs_block=0, rhs_lanes=0,
+                      out=None):
         if out is None:
             out = self.half_spinor(prec, nrhs)
         _check(lib().whmc_apply_H_multi(self._h, _ptr(out), _ptr(inp), out_parity, int(dagger), prec, links, nrhs,
-                                        rhs_block))
+                                        rhs_block, rhs_lanes))
         return out
 
     def autotune(self, prec, links, nrhs):
-        nb, us = ctypes.c_int(), ctypes.c_double()
-        _check(lib().whmc_autotune(self._h, prec, links, nrhs, ctypes.byref(nb), ctypes.byref(us)))
-        return nb.value, us.value
+        """-> (rhs_block, rhs_lanes, microseconds per launch) of the fastest multi-RHS blocking"""
+        nb, lanes, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(lib().whmc_autotune(self._h, prec, links, nrhs, ctypes.byref(nb), ctypes.byref(lanes), ctypes.byref(us)))
+        return nb.value, lanes.value, us.value
 
     def apply_Moo(self, inp, kappa, dagger=False, out=None):
         out = self.half_spinor() if out is None else out

@@ -13,18 +13,20 @@ from gpu_util import make_ctx, pack_half, rel_err, unpack_half
 pytestmark = pytest.mark.gpu
 
 KAPPAS = [0.150, 0.153, 0.156, 0.1575]
+LOW_PREC_BLOCKINGS = [(1, 1), (1, 2), (2, 1), (2, 2), (4, 1), (4, 2)]
 
 
 @pytest.mark.parametrize("nrhs", [1, 3, 5])
-@pytest.mark.parametrize("nb", [1, 2, 3, 4])
-@pytest.mark.parametrize("dims", [(4, 4, 6, 6), (4, 8, 16, 16)])
-def test_multi_hop_fp64_parity(nrhs, nb, dims):
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+# (4, 8, 16, 16): time slices of 8 blocks, one per XCD; (4, 12, 16, 16): 12 blocks, with padding
+@pytest.mark.parametrize("dims", [(4, 4, 6, 6), (4, 8, 16, 16), (4, 12, 16, 16)])
+def test_multi_hop_fp64_parity(nrhs, lanes, dims):
     lat = Lattice(dims)
     U = synth.haar_links(dims, 5000)
     xs = np.stack([synth.gaussian_spinor(lat.Vh, 5001 + r) for r in range(nrhs)])
     ctx = make_ctx(dims, U)
     for par, dag in [(0, 0), (1, 1)]:
-        out = ctx.apply_H_multi(pack_half(ctx, xs), par, nrhs, dagger=dag, rhs_block=nb)
+        out = ctx.apply_H_multi(pack_half(ctx, xs), par, nrhs, dagger=dag, rhs_block=1, rhs_lanes=lanes)
         got = unpack_half(ctx, out, nrhs).reshape(nrhs, lat.Vh, 4, 3)
         for r in range(nrhs):
             assert rel_err(got[r], dirac.apply_Hblock(lat, U, xs[r], par, dagger=bool(dag))) < 1e-12
@@ -39,8 +41,8 @@ def test_multi_hop_low_precision(prec, tol):
     xs = np.stack([synth.gaussian_spinor(lat.Vh, 5011 + r) for r in range(nrhs)])
     ctx = make_ctx(dims, U)
     xin = ctx.convert_spinor(pack_half(ctx, xs), whmc.F64, prec, nrhs)
-    for nb in (1, 2, 4):
-        out = ctx.apply_H_multi(xin, 1, nrhs, prec=prec, links=whmc.L12, rhs_block=nb)
+    for nb, lanes in LOW_PREC_BLOCKINGS:
+        out = ctx.apply_H_multi(xin, 1, nrhs, prec=prec, links=whmc.L12, rhs_block=nb, rhs_lanes=lanes)
         got = unpack_half(ctx, ctx.convert_spinor(out, prec, whmc.F64, nrhs), nrhs).reshape(nrhs, lat.Vh, 4, 3)
         for r in range(nrhs):
             assert rel_err(got[r], dirac.apply_Hblock(lat, U, xs[r], 1)) < tol
@@ -49,22 +51,40 @@ def test_multi_hop_low_precision(prec, tol):
 def test_autotuner_returns_a_valid_block():
     dims = (8, 8, 8, 8)
     ctx = make_ctx(dims, synth.smooth_links(dims, 5020))
-    nb, us = ctx.autotune(whmc.F64, whmc.L18, 8)
-    assert 1 <= nb <= 4 and us > 0
-    assert ctx.autotune(whmc.F64, whmc.L18, 8)[0] == nb     # remembered
+    nb, lanes, us = ctx.autotune(whmc.F64, whmc.L18, 8)
+    assert nb == 1 and lanes in (1, 2, 4) and us > 0
+    assert ctx.autotune(whmc.F64, whmc.L18, 8)[:2] == (nb, lanes)     # remembered
+    nb, lanes, us = ctx.autotune(whmc.F16, whmc.L12, 8)
+    assert (nb, lanes) in LOW_PREC_BLOCKINGS and us > 0
 
 
-@pytest.mark.parametrize("prec,nrhs,nb,dims", [(whmc.F64, 4, 0, (4, 4, 4, 8)), (whmc.F64, 5, 2, (4, 4, 4, 8)),
-                                               (whmc.F32, 4, 0, (4, 4, 4, 8)), (whmc.F16, 6, 3, (4, 4, 4, 8)),
-                                               (whmc.F64, 2, 2, (4, 8, 16, 16))])
-def test_masked_multi_rhs_cg(prec, nrhs, nb, dims):
+@pytest.mark.parametrize("prec,nb,lanes", [(whmc.F64, 2, 1), (whmc.F64, 1, 3), (whmc.F64, 1, 8), (whmc.F32, 3, 1),
+                                           (whmc.F16, 4, 4)])
+def test_unsupported_blocking_rejected(prec, nb, lanes):
+    dims = (4, 4, 4, 4)
+    lat = Lattice(dims)
+    ctx = make_ctx(dims, synth.haar_links(dims, 5021))
+    xs = pack_half(ctx, np.stack([synth.gaussian_spinor(lat.Vh, 5022 + r) for r in range(3)]))
+    xin = xs if prec == whmc.F64 else ctx.convert_spinor(xs, whmc.F64, prec, 3)
+    links = whmc.L18 if prec == whmc.F64 else whmc.L12
+    with pytest.raises(whmc.WhmcError) as e:
+        ctx.apply_H_multi(xin, 0, 3, prec=prec, links=links, rhs_block=nb, rhs_lanes=lanes)
+    assert e.value.status == 1   # EARG
+
+
+@pytest.mark.parametrize("prec,nrhs,nb,lanes,dims", [(whmc.F64, 4, 0, 0, (4, 4, 4, 8)), (whmc.F64, 5, 1, 2, (4, 4, 4, 8)),
+                                                     (whmc.F32, 4, 0, 0, (4, 4, 4, 8)), (whmc.F16, 6, 4, 2, (4, 4, 4, 8)),
+                                                     (whmc.F32, 5, 2, 1, (4, 4, 4, 8)),
+                                                     (whmc.F64, 2, 1, 4, (4, 8, 16, 16)),
+                                                     (whmc.F32, 3, 2, 2, (4, 12, 16, 16))])
+def test_masked_multi_rhs_cg(prec, nrhs, nb, lanes, dims):
     lat = Lattice(dims)
     U = synth.smooth_links(dims, 5030)
     kappas = [KAPPAS[r % 4] for r in range(nrhs)]
     bs = np.stack([synth.gaussian_spinor(lat.Vh, 4000 + r) for r in range(nrhs)])
     ctx = make_ctx(dims, U)
     prm = whmc.cg_params(tol=1e-10, prec=prec, links=whmc.L18 if prec == whmc.F64 else whmc.L12, delta=0.1,
-                         rhs_block=nb)
+                         rhs_block=nb, rhs_lanes=lanes)
     x, st = ctx.cg_solve(pack_half(ctx, bs), kappas, prm)
     got = unpack_half(ctx, x, nrhs).reshape(nrhs, lat.Vh, 4, 3)
     iters = [s["iters"] for s in st]

@@ -14,9 +14,12 @@ pytestmark = pytest.mark.gpu
 
 # several tiles and a ragged tail (Vh = 288, 1728 are not multiples of 256), the degenerate 2^4;
 # (6, 8, 16, 16) has time slices of 1024 = 8 x 128 sites, so the stencil kernels give each XCD one
-# eighth of every slice (the schedule used at 32^3 x 64) instead of one eighth of the lattice
+# eighth of every slice (the schedule used at 32^3 x 64) instead of one eighth of the lattice;
+# (4, 12, 16, 16) has slices of 12 blocks, cut 1/2/1/2/... per XCD with idle padding workgroups
+# (the schedule used at 24^3 x 48)
 SLICED = (6, 8, 16, 16)
-DIMS = [(2, 2, 2, 2), (4, 4, 4, 4), (4, 4, 6, 6), (6, 4, 6, 8), (8, 6, 4, 12), SLICED]
+PADDED = (4, 12, 16, 16)
+DIMS = [(2, 2, 2, 2), (4, 4, 4, 4), (4, 4, 6, 6), (6, 4, 6, 8), (8, 6, 4, 12), SLICED, PADDED]
 
 
 @pytest.mark.parametrize("dims", DIMS)
@@ -33,7 +36,7 @@ def test_hop_eo_fp64_parity(dims, out_parity, dagger):
         assert rel_err(unpack_half(ctx, out), ref) < 1e-12, links
 
 
-@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 6, 8), SLICED])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 6, 8), SLICED, PADDED])
 def test_full_H_parity(dims):
     lat = Lattice(dims)
     U = synth.smooth_links(dims, 1010)
@@ -45,7 +48,7 @@ def test_full_H_parity(dims):
         assert rel_err(unpack_full(ctx, out), ref) < 1e-12
 
 
-@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (4, 4, 6, 6), SLICED])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (4, 4, 6, 6), SLICED, PADDED])
 def test_Moo_and_MdagM_parity(dims):
     lat = Lattice(dims)
     U = synth.haar_links(dims, 1020)
