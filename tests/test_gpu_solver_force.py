@@ -164,3 +164,68 @@ def test_md_reversibility_and_dtau_scaling():
             delta = float(np.sum(np.abs(ctx.export_gauge().cpu().numpy() - U) ** 2))
             assert delta < 1e-20
     assert 3.0 < dHs[0] / dHs[1] < 5.5 and 3.3 < dHs[1] / dHs[2] < 4.8, dHs
+
+
+# lattices whose time slices are 8 and 12 blocks of 128 sites: the link-parallel force kernels then
+# run the per-XCD slice schedule (with idle padding workgroups for 12) with 8 (parity, mu) groups
+# per block; (2, 2, 2, 4) has extents 2, where x + mu = x - mu and staples wrap twice
+@pytest.mark.parametrize("dims", [(4, 8, 16, 16), (4, 12, 16, 16), (2, 2, 2, 4)])
+def test_gauge_force_parity_split_and_degenerate_lattices(dims):
+    lat = Lattice(dims)
+    U = synth.smooth_links(dims, 2100) if dims[1] > 2 else synth.haar_links(dims, 2100)
+    ctx = make_ctx(dims, U)
+    assert ctx.plaquette() == pytest.approx(gauge.plaquette(lat, U), rel=1e-13)
+    F = ctx.force(ctx.half_spinor(), 0, 0, 0, 0.15, 5.6, flags=whmc.FORCE_GAUGE)
+    assert rel_err(algebra_to_numpy(ctx, F), gauge.gauge_force(lat, U, 5.6)) < 1e-12
+
+
+def test_pf_force_parity_padded_lattice():
+    dims = (4, 12, 16, 16)
+    lat = Lattice(dims)
+    U = synth.smooth_links(dims, 2110)
+    kappa = 0.12
+    phi = synth.gaussian_spinor(lat.Vh, 2111)
+    ctx = make_ctx(dims, U)
+    F = ctx.force(pack_half(ctx, phi), 0, 0, 0, kappa, 5.6, solver=whmc.cg_params(tol=1e-14))
+    assert rel_err(algebra_to_numpy(ctx, F), force.pf_force_eo(lat, U, phi, kappa, tol=1e-14)) < 1e-10
+
+
+@pytest.mark.parametrize("prec", [whmc.F64, whmc.F16])
+def test_cg_zero_source_and_iteration_limit(prec):
+    dims = (4, 4, 4, 8)
+    lat = Lattice(dims)
+    U = synth.smooth_links(dims, 2120)
+    ctx = make_ctx(dims, U)
+    links = whmc.L18 if prec == whmc.F64 else whmc.L12
+    # b = 0: x = 0 at once, converged
+    x, st = ctx.cg_solve(pack_half(ctx, np.zeros((lat.Vh, 4, 3), complex)), [0.156],
+                         whmc.cg_params(tol=1e-10, prec=prec, links=links))
+    assert st[0]["converged"] and st[0]["true_residual"] == 0.0 and not unpack_half(ctx, x).any()
+    # an iteration limit far below what 1e-12 needs: ENOCONV, with the stats still filled in
+    b = pack_half(ctx, synth.gaussian_spinor(lat.Vh, 2121))
+    prm = whmc.cg_params(tol=1e-12, maxiter=4, check_every=2, prec=prec, links=links)
+    with pytest.raises(whmc.WhmcError) as e:
+        ctx.cg_solve(b, [0.156], prm)
+    assert e.value.status == 3   # ENOCONV
+    _, st = ctx.cg_solve(b, [0.156], prm, raise_on_noconv=False)
+    assert not st[0]["converged"] and st[0]["true_residual"] > 1e-12 and st[0]["iters"] >= 4
+
+
+def test_multi_cg_with_a_zero_rhs_and_sixteen_rhs():
+    dims = (2, 2, 4, 8)
+    lat = Lattice(dims)
+    U = synth.smooth_links(dims, 2130)
+    ctx = make_ctx(dims, U)
+    kappas = [0.150 + 0.0005 * r for r in range(16)]
+    bs = np.stack([synth.gaussian_spinor(lat.Vh, 2131 + r) for r in range(16)])
+    bs[5] = 0.0
+    x, st = ctx.cg_solve(pack_half(ctx, bs), kappas, whmc.cg_params(tol=1e-11))
+    got = unpack_half(ctx, x, 16).reshape(16, lat.Vh, 4, 3)
+    assert all(s["converged"] for s in st)
+    assert not got[5].any() and st[5]["true_residual"] == 0.0
+    for r in (0, 15):
+        ref, _, _ = cg(lambda v: dirac.apply_MooDagMoo(lat, U, v, kappas[r]), bs[r], tol=1e-14)
+        assert rel_err(got[r], ref) < 1e-9
+    with pytest.raises(whmc.WhmcError) as e:   # at most 16 right-hand sides
+        ctx.cg_solve(pack_half(ctx, np.concatenate([bs, bs[:1]])), kappas + [0.15], whmc.cg_params())
+    assert e.value.status == 1   # EARG
