@@ -222,6 +222,14 @@ def extras(ctx, whmc, torch, np, stream, Vh):
         cgr[name]["speedup_vs_fp64"] = round(t["fp64"] / t[name], 3)
     out["cg_32x64_kappa0.1575"] = cgr
 
+    # M_oo x = b to |b - M_oo x| / |b| <= 1e-10: BiCGstab on M_oo (the paper's solver) against CG on
+    # the normal equations M_oo^dag M_oo x = M_oo^dag b (both FP64, 18-real links; 4 hops per
+    # iteration).  BiCGstab needs the spectrum of M_oo in the right half-plane: on the smooth
+    # synthetic fields of width 0.3 - 0.55 kappa = 0.1575 is past or at their critical kappa, so this
+    # comparison runs on a rough field (width 0.8, plaquette ~0.15) at kappa = 0.156; on thermalised
+    # beta = 5.6 fields the ensemble driver (--compare-solvers) makes the same comparison
+    out["solve_Moo_32x64_width0.8_kappa0.156"] = bicgstab_vs_cgne(whmc, torch)
+
     out["multi_rhs_24x48"] = multi_rhs(whmc, torch, stream)
     out["hmc_32x64"] = hmc_section(ctx, whmc, torch, stream, Vh)
 
@@ -231,6 +239,26 @@ def extras(ctx, whmc, torch, np, stream, Vh):
     out["force_kappa4_nt15_ms"] = round(ms, 1)
     log(f"[bench] filtered force (kappa^4, n_t=15): {ms:.1f} ms")
     return out
+
+
+def bicgstab_vs_cgne(whmc, torch):
+    from paper_1805_03560_amd import synth
+    U = synth.smooth_links(DIMS, 3005, width=0.8, threads=min(16, os.cpu_count() or 1))
+    ctx = whmc.Context(DIMS, device=0)
+    ctx.load_gauge(torch.from_numpy(U).to(ctx.device), unitarity_tol=1e-11)
+    del U
+    stream = ctx.stream
+    Vh = ctx.Vh
+    b = ctx.pack_spinor(torch.from_numpy(synth.gaussian_spinor(Vh, 3006)).to(ctx.device), 0)
+    from paper_1805_03560_amd.ensemble import compare_solvers
+    try:
+        res = compare_solvers(ctx, whmc, torch, b, 0.156)
+        log(f"[bench] M_oo x = b: BiCGstab {res['bicgstab']}, CGNE {res['cg_normal_equations']}")
+    except whmc.WhmcError as e:
+        res = {"error": str(e)}
+        log(f"[bench] M_oo x = b: {e}")
+    ctx.close()
+    return res
 
 
 def multi_rhs(whmc, torch, stream):

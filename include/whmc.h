@@ -170,6 +170,16 @@ typedef struct whmc_cg_stats {
 whmc_status whmc_cg_solve(whmc_ctx* ctx, double* x, const double* b, const double* kappas, int nrhs,
                           const whmc_cg_params* params, whmc_cg_stats* stats);
 
+/* Solve M_oo(kappa) x = b (dagger = 0) or M_oo(kappa)^dag x = b (dagger = 1) for one odd-site half
+ * field (FP64 whmc layout) by BiCGstab, the Krylov solver the paper uses (Sec. 4), from x = 0 until
+ * the true FP64 residual |b - A x| / |b| <= params->tol.  params->prec must be WHMC_F64 (else
+ * WHMC_EUNSUP); params->links selects 18- or 12-real links for the iteration (the true residual
+ * always uses 18-real links); maxiter and check_every as for whmc_cg_solve; one iteration applies
+ * A twice.  A breakdown restarts from the true residual (at most 4 passes).  stats (may be NULL)
+ * receives one entry.  Returns WHMC_ENOCONV if tol is not reached. */
+whmc_status whmc_bicgstab_solve(whmc_ctx* ctx, double* x, const double* b, double kappa, int dagger,
+                                const whmc_cg_params* params, whmc_cg_stats* stats);
+
 /* ------------------------------------------------------------------ filter, actions, forces
  * Hopping-parameter-expansion filter (Sec. 2, 2.2): with K = kappa^2 H_oe H_eo,
  *   M~ = M_oo exp(sum_{j<=k} K^j / j),  M~^{-1} = sum_n b_n K^n + alpha M_oo^{-1}.

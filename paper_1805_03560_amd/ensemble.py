@@ -55,8 +55,43 @@ def parse(argv=None):
                          "bitwise reproducible: the blocking sets the summation order of the reductions)")
     ap.add_argument("--forces", action="store_true", help="record (F,F) of both forces at each start")
     ap.add_argument("--max-seconds", type=float, default=None, help="stop after this much wall time")
+    ap.add_argument("--compare-solvers", action="store_true",
+                    help="at the end, time BiCGstab on M_oo against CG on the normal equations on the final field")
     ap.add_argument("--out", required=True)
     return ap.parse_args(argv)
+
+
+def compare_solvers(ctx, whmc, torch, b, kappa):
+    """BiCGstab on M_oo vs CG on the normal equations for M_oo x = b, both to |b - M x| / |b| <= 1e-10"""
+    res = {}
+    stream = ctx.stream
+    bn = float(torch.linalg.vector_norm(b))
+
+    def timed(fn):
+        fn()   # warm-up of this path
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        out = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1)
+
+    (x, st), ms = timed(lambda: ctx.bicgstab_solve(b, kappa, params=whmc.cg_params(tol=1e-10)))
+    r = float(torch.linalg.vector_norm(b - ctx.apply_Moo(x, kappa))) / bn
+    res["bicgstab"] = {"ms": round(ms, 2), "iters": st["iters"], "hops": 4 * st["iters"], "residual_Moo": r}
+    # CG on the normal equations: tolerance on |M^dag b - A x| / |M^dag b| tightened until the
+    # M_oo residual is below 1e-10 as well
+    bd = ctx.apply_Moo(b, kappa, dagger=True)
+    for tol in (1e-10, 3e-11, 1e-11):
+        (xs, sts), ms = timed(lambda: ctx.cg_solve(bd, [kappa], whmc.cg_params(tol=tol)))
+        r = float(torch.linalg.vector_norm(b - ctx.apply_Moo(xs, kappa))) / bn
+        if r <= 1e-10:
+            break
+    res["cg_normal_equations"] = {"ms": round(ms, 2), "iters": sts[0]["iters"], "hops": 4 * sts[0]["iters"],
+                                  "residual_Moo": r, "cg_tol": tol}
+    res["speedup_bicgstab_vs_cgne"] = round(res["cg_normal_equations"]["ms"] / res["bicgstab"]["ms"], 3)
+    return res
 
 
 def draws(torch, dev, seed, traj, n_pi, n_eta):
@@ -121,7 +156,12 @@ def main(argv=None):
         if a.max_seconds is not None and time.time() - t_start > a.max_seconds:
             break
     np.save(os.path.join(a.out, "U_last.npy"), ctx.export_gauge().cpu().numpy())
-    json.dump({"next_first": a.first + done, "args": vars(a)}, open(os.path.join(a.out, "state.json"), "w"))
+    state = {"next_first": a.first + done, "args": vars(a)}
+    if a.compare_solvers:
+        _, eta, _ = draws(torch, dev, a.seed, -1, 0, n_eta)
+        state["solvers"] = compare_solvers(ctx, whmc, torch, eta, a.kappa)
+        print(f"[ensemble] M_oo x = b on the final field: {state['solvers']}", flush=True)
+    json.dump(state, open(os.path.join(a.out, "state.json"), "w"))
     print(f"[ensemble] {done} trajectories in {time.time() - t_start:.1f}s; next --first {a.first + done}",
           flush=True)
     ctx.close()

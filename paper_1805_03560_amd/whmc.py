@@ -89,6 +89,8 @@ _SIGS = {
                             ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "whmc_autotune": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "whmc_bicgstab_solve": ([_P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.POINTER(CGParams),
+                             ctypes.POINTER(CGStats)], ctypes.c_int),
     "whmc_apply_MdagM": ([_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int], ctypes.c_int),
     "whmc_cg_solve": ([_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.POINTER(CGParams),
                        ctypes.POINTER(CGStats)], ctypes.c_int),
@@ -284,6 +286,17 @@ class Context:
         if rc != 0 and (rc != 3 or raise_on_noconv):
             _check(rc)
         return x, [s.as_dict() for s in stats]
+
+    def bicgstab_solve(self, b, kappa, dagger=False, params=None, x=None, raise_on_noconv=True):
+        """x = M_oo(kappa)^{-1} b (dagger: M_oo^dag x = b) by BiCGstab, FP64"""
+        params = params or cg_params()
+        x = self.half_spinor(F64) if x is None else x
+        st = CGStats()
+        rc = lib().whmc_bicgstab_solve(self._h, _ptr(x), _ptr(b), float(kappa), int(bool(dagger)),
+                                       ctypes.byref(params), ctypes.byref(st))
+        if rc != 0 and (rc != 3 or raise_on_noconv):
+            _check(rc)
+        return x, st.as_dict()
 
     # ------------------------------------------------------------ actions, forces, HMC
     def heatbath_phi(self, eta, k, n_t, n_max, kappa):
