@@ -254,9 +254,10 @@ typedef struct whmc_traj_result {
   double dH, H0, H1;
   int accepted;
   double plaquette;       /* of the field kept after the accept/reject step */
-  long long cg_iters;     /* total solver iterations in the trajectory */
+  long long cg_iters;     /* total M_oo^dag M_oo solver iterations in the trajectory */
   int n_solves;
   double seconds;
+  long long poly_iters;   /* CG iterations on p_j^dag p_j in the rooted heat bath (0 otherwise) */
 } whmc_traj_result;
 
 whmc_status whmc_hmc_trajectory(whmc_ctx* ctx, const whmc_hmc_params* p, const double* pi0, const double* eta,
@@ -269,6 +270,84 @@ whmc_status whmc_md_integrate(whmc_ctx* ctx, const whmc_hmc_params* p, double* p
 /* Hamiltonian H = (1/2)(Pi,Pi) + S~_G + S~_PF for the context's gauge field. */
 whmc_status whmc_hamiltonian(whmc_ctx* ctx, const whmc_hmc_params* p, const double* pi, const double* phi,
                              double* H);
+
+/* ------------------------------------------------------------------ rooted polynomials (Sec. 2.1)
+ * Starting from M_1 = M~ of the kappa^(2k) filter (M_oo for k = 0) and with x = K, the chain
+ *   p_j(x) = W_j^{-1} = Taylor polynomial of degree n_j of M_j(x)^{-1/N},   M_{j+1} = p_j(x)^N M_j,
+ * j = 1 .. jmax (one root order N for all j, as in the paper's runs), leaves the remainder
+ *   M_{jmax+1}^{-1} = sum_n b_n K^n + alpha M_oo^{-1}                      (eq. restM).
+ * Since det M~ = prod_j det(W_j)^N det M_{jmax+1}, two flavours are represented by jmax*N + 1
+ * pseudo-fermion fields with the terms
+ *   S_j = sum_{i=1..N} |p_j(K) phi_{j,i}|^2   (j = 1 .. jmax),
+ *   S_r = |(sum_{n<=n_max} b_n K^n + alpha M_oo^{-1}) phi_r|^2   (term jmax + 1),
+ * plus the gauge action at beta (+ 96 kappa^4 for k = 2).  n_t truncates the remainder series in
+ * the force, n_max in the action and the heat bath.  jmax = 0 is the kappa^(2k) filter itself.
+ * Fields: phi and eta hold the jmax*N + 1 odd-site FP64 fields (whmc layout) back to back in the
+ * order phi_{1,1} .. phi_{1,N}, phi_{2,1}, ..., phi_r.  Scratch grows with max(n_j, n_t) + 1 fields
+ * of each of four kinds (the Horner vectors of the force). */
+#define WHMC_MAX_POLY 4
+#define WHMC_ROOTED_MAX_N 1000
+typedef struct whmc_rooted {
+  int N;                   /* root order, 1 .. 64 */
+  int jmax;                /* number of polynomials, 0 .. WHMC_MAX_POLY */
+  int n[WHMC_MAX_POLY];    /* degrees n_1 .. n_jmax, each 1 .. WHMC_ROOTED_MAX_N */
+  int k;                   /* filter order of M_1: 0, 1 or 2 */
+  int n_t;                 /* remainder truncation in the force, 0 .. WHMC_ROOTED_MAX_N */
+  int n_max;               /* remainder (and M~ eta) truncation in action and heat bath, same range */
+} whmc_rooted;
+
+/* Coefficient tables on the host, in extended precision: p receives p_1[0..n_1], p_2[0..n_2], ...
+ * back to back (sum_j (n_j + 1) doubles), b receives b[0..nb] (nb <= WHMC_ROOTED_MAX_N), alpha the
+ * alpha of eq. (restM).  Any output may be NULL.  Needs no GPU. */
+whmc_status whmc_rooted_coefficients(const whmc_rooted* r, double* p, double* b, int nb, double* alpha);
+
+/* Heat bath (eq. initPseudo for each term): phi_{j,i} = p_j(K)^{-1} eta_{j,i} by CG on
+ * p_j^dag p_j to solver->tol (relative residual; FP64; solver->maxiter bounds each solve),
+ * phi_r = prod_j p_j(K)^N M~ eta_r with M~ eta truncated at n_max.  solver may be NULL (1e-12).
+ * iters (may be NULL) receives the total CG iterations.  WHMC_ENOCONV if a solve hits maxiter. */
+whmc_status whmc_rooted_heatbath(whmc_ctx* ctx, double* phi, const double* eta, const whmc_rooted* r, double kappa,
+                                 const whmc_cg_params* solver, long long* iters);
+
+/* S[0 .. jmax]: S_1 .. S_jmax and S_r (at n_max).  solver (may be NULL: FP64 CG to 1e-12) inverts
+ * M_oo^dag M_oo for the alpha term. */
+whmc_status whmc_rooted_action(whmc_ctx* ctx, double* S, const double* phi, const whmc_rooted* r, double kappa,
+                               const whmc_cg_params* solver);
+
+/* Force of one term in the algebra layout (the Horner scheme of Sec. 2 with the term's
+ * coefficients; the polynomial terms need no solve): term 1 .. jmax is S_j summed over its N
+ * fields, term jmax + 1 is S_r with the series truncated at n_t, term 0 is all of them.
+ * flags: WHMC_FORCE_ACCUMULATE adds to F instead of overwriting it. */
+whmc_status whmc_rooted_force(whmc_ctx* ctx, double* F, const double* phi, const whmc_rooted* r, int term,
+                              double kappa, const whmc_cg_params* solver, int flags);
+
+/* Multi-level trajectory with the rooted action (Sec. 2.1, 4.2): the gauge action on level 0 and
+ * term j on level j, the remainder on level jmax + 1.  One (half, for Omelyan) step of level l
+ * holds msub[l-1] steps of level l - 1; the remainder takes m steps over tau.  In the paper's
+ * notation (jmax = 2) msub = {m_0, m_1, m_2}.  Otherwise as whmc_hmc_trajectory; eta holds the
+ * jmax*N + 1 Gaussian sources, heatbath_solver drives the polynomial heat baths. */
+typedef struct whmc_rooted_hmc_params {
+  double beta;
+  double kappa;
+  whmc_rooted rooted;
+  int integrator;                 /* whmc_integrator */
+  double lambda;                  /* Omelyan parameter */
+  int m;                          /* remainder steps per trajectory */
+  int msub[WHMC_MAX_POLY + 1];    /* msub[l-1]: level l-1 steps per step of level l, l = 1 .. jmax+1 */
+  double tau;
+  whmc_cg_params md_solver;
+  whmc_cg_params action_solver;
+  whmc_cg_params heatbath_solver;
+} whmc_rooted_hmc_params;
+
+whmc_status whmc_rooted_trajectory(whmc_ctx* ctx, const whmc_rooted_hmc_params* p, const double* pi0,
+                                   const double* eta, double u, whmc_traj_result* res);
+
+/* Molecular dynamics only, with the jmax*N + 1 fields phi fixed (pi integrated in place). */
+whmc_status whmc_rooted_md_integrate(whmc_ctx* ctx, const whmc_rooted_hmc_params* p, double* pi, const double* phi);
+
+/* H = (1/2)(Pi,Pi) + S_G + sum_j S_j + S_r for the context's gauge field. */
+whmc_status whmc_rooted_hamiltonian(whmc_ctx* ctx, const whmc_rooted_hmc_params* p, const double* pi,
+                                    const double* phi, double* H);
 
 #ifdef __cplusplus
 }

@@ -51,10 +51,10 @@ def _level_forces(lat, phi_o, p):
     ]
 
 
-def integrate(lat, U, pi, phi_o, p):
-    """molecular dynamics over tau; returns (U', pi')."""
-    forces = _level_forces(lat, phi_o, p)
-    steps = [p.m0, p.m]                       # substeps of level 0 per level-1 block, level-1 steps
+def integrate_levels(lat, U, pi, forces, nsub, m, integrator, lam, tau):
+    """molecular dynamics over tau with levels 0..L: forces[l](U) is the force of level l, one
+    (half, for Omelyan) step of level l >= 1 holds nsub[l-1] steps of level l-1, and level L
+    takes m steps.  Returns (U', pi')."""
     state = {"U": U.copy(), "pi": pi.copy()}
 
     def P(level, eps):
@@ -63,8 +63,8 @@ def integrate(lat, U, pi, phi_o, p):
     def T(eps):
         state["U"] = np.einsum("...ab,...bc->...ac", expm_ah(eps * from_coords(state["pi"])), state["U"])
 
-    omel = p.integrator == "omelyan"
-    lam = p.lam if omel else 0.5
+    omel = integrator == "omelyan"
+    lam = lam if omel else 0.5
 
     def run(level, eps):
         if omel:
@@ -83,14 +83,20 @@ def integrate(lat, U, pi, phi_o, p):
         if level == 0:
             T(span)
         else:
-            n = steps[level - 1]
+            n = nsub[level - 1]
             for _ in range(n):
                 run(level - 1, span / n)
 
-    eps_top = p.tau / p.m
-    for _ in range(p.m):
-        run(1, eps_top)
+    top = len(forces) - 1
+    for _ in range(m):
+        run(top, tau / m)
     return state["U"], state["pi"]
+
+
+def integrate(lat, U, pi, phi_o, p):
+    """molecular dynamics over tau (gauge on level 0, m0 steps per level-1 block; pseudo-fermion
+    on level 1, m steps); returns (U', pi')."""
+    return integrate_levels(lat, U, pi, _level_forces(lat, phi_o, p), [p.m0], p.m, p.integrator, p.lam, p.tau)
 
 
 def trajectory(lat, U0, pi0, eta_o, u, p):

@@ -20,13 +20,19 @@ Since det M~ = prod_j (det W_j)^N det M_{j_max+1}, two flavours are represented 
     phi_r = M_{j_max+1} eta = prod_j p_j(K)^N M~ eta.
 The force of |(sum_n c_n K^n + a M_oo^{-1}) phi|^2 is the Horner construction of Sec. 2 for any
 coefficients c_n and a; with a = 0 (the polynomial fields) it has no inverse and no (X~, Y~) pair.
+
+HMC (Sec. 4.2): the runs use several time scales with step counts m_0, m_1, m_2 and m.  Reading:
+the gauge action sits on level 0, the term of p_j on level j and the remainder on level
+j_max + 1 (forces ordered from the largest, cheapest to the smallest, most expensive); one step
+of level l holds m_{l-1} steps of level l - 1, and the remainder takes m steps per trajectory.
 """
+from dataclasses import dataclass
 from fractions import Fraction
 
 import mpmath
 import numpy as np
 
-from . import dirac, hpe
+from . import dirac, gauge, hmc, hpe
 from .force import expand_pair_eo, force_from_pairs
 from .solve import cg
 
@@ -58,9 +64,9 @@ def _log(p, n):
 
 def polynomials(N, ns, k):
     """[p_1, p_2, ...] as exact coefficient lists of degrees ns."""
-    n = max(ns)
+    n = max(ns, default=0)
     logM = [Fraction(0)] + [Fraction(-1, i) for i in range(1, n + 1)]   # log(1 - x)
-    for i in range(1, k + 1):
+    for i in range(1, min(k, n) + 1):
         logM[i] += Fraction(1, i)                                          # + sum_{i<=k} x^i / i
     out = []
     for nj in ns:
@@ -167,3 +173,68 @@ def series_force(lat, U, phi, c, a, kappa, tol=1e-14):
             X = hpe._next_X(lat, U, X, kappa)
         pairs.append(expand_pair_eo(lat, U, X, Ys[i]))
     return force_from_pairs(lat, U, pairs, kappa ** 2)
+
+
+# ---------------------------------------------------------------- HMC with the rooted action
+
+@dataclass
+class RootedHMCParams:
+    beta: float = 5.6
+    kappa: float = 0.1575
+    N: int = 2
+    ns: tuple = (4, 8)          # degrees n_1 .. n_jmax
+    k: int = 0                  # filter of M_1 = M~
+    n_t: int = 20               # remainder truncation in the force
+    n_max: int = 40             # remainder truncation in action and heat bath
+    integrator: str = "leapfrog"
+    lam: float = 1.0 / 6.0
+    m: int = 4                  # remainder steps per trajectory
+    msub: tuple = (2, 2, 2)     # m_0, m_1, ..., m_jmax
+    tau: float = 1.0
+    tol: float = 1e-13
+
+
+def rooted_hamiltonian(lat, U, pi, phis, p):
+    """(1/2)(Pi,Pi) + S_G + sum_j sum_i |p_j(K) phi_{j,i}|^2 + |remainder phi_r|^2 (at n_max)."""
+    ps, b, al = coefficients_f64(p.N, p.ns, p.k, p.n_max)
+    H = 0.5 * float(np.sum(pi * pi)) + gauge.gauge_action(lat, U, p.beta + hpe.delta_beta(p.kappa, p.k))
+    for j, pj in enumerate(ps):
+        for i in range(p.N):
+            H += poly_action(lat, U, phis[j * p.N + i], pj, p.kappa)
+    return H + remainder_action(lat, U, phis[-1], b, al, p.kappa, p.tol)
+
+
+def rooted_forces(lat, phis, p):
+    """forces of the levels: gauge, the polynomial terms, the remainder (at n_t)."""
+    ps, b, al = coefficients_f64(p.N, p.ns, p.k, p.n_t)
+    beta_eff = p.beta + hpe.delta_beta(p.kappa, p.k)
+    out = [lambda U: gauge.gauge_force(lat, U, beta_eff)]
+    for j, pj in enumerate(ps):
+        out.append(lambda U, j=j, pj=pj: sum(series_force(lat, U, phis[j * p.N + i], pj, 0.0, p.kappa, p.tol)
+                                             for i in range(p.N)))
+    out.append(lambda U: series_force(lat, U, phis[-1], b, al, p.kappa, p.tol))
+    return out
+
+
+def rooted_integrate(lat, U, pi, phis, p):
+    return hmc.integrate_levels(lat, U, pi, rooted_forces(lat, phis, p), list(p.msub[:len(p.ns) + 1]), p.m,
+                                p.integrator, p.lam, p.tau)
+
+
+def rooted_heatbath(lat, U, etas, p):
+    ps, _, _ = coefficients_f64(p.N, p.ns, p.k, 0)
+    phis = [poly_heatbath(lat, U, etas[j * p.N + i], ps[j], p.kappa, p.tol)
+            for j in range(len(ps)) for i in range(p.N)]
+    return phis + [remainder_heatbath(lat, U, etas[-1], ps, p.N, p.kappa, p.k, p.n_max)]
+
+
+def rooted_trajectory(lat, U0, pi0, etas, u, p):
+    """heat bath of all jmax*N + 1 fields, H0, multi-level MD, H1, Metropolis."""
+    phis = rooted_heatbath(lat, U0, etas, p)
+    H0 = rooted_hamiltonian(lat, U0, pi0, phis, p)
+    U1, pi1 = rooted_integrate(lat, U0, pi0, phis, p)
+    H1 = rooted_hamiltonian(lat, U1, pi1, phis, p)
+    dH = H1 - H0
+    acc = bool(u < np.exp(-dH))
+    return {"U": U1 if acc else U0, "U_end": U1, "pi_end": pi1, "dH": dH, "accepted": acc, "H0": H0, "H1": H1,
+            "phis": phis}

@@ -55,9 +55,9 @@ static void coefficients(int k, int n, std::vector<double>& b, std::vector<doubl
   }
 }
 
-static double delta_beta(double kappa, int k) { return k >= 2 ? 96.0 * kappa * kappa * kappa * kappa : 0.0; }
+double delta_beta(double kappa, int k) { return k >= 2 ? 96.0 * kappa * kappa * kappa * kappa : 0.0; }
 
-static whmc_cg_params default_solver() {
+whmc_cg_params default_solver() {
   whmc_cg_params p{};
   p.tol = 1e-12;
   p.maxiter = 10000;
@@ -78,38 +78,21 @@ static whmc_status check_filter(const whmc_filter* f) {
   return WHMC_OK;
 }
 
-struct Fields {
-  whmc_ctx* c;
-  size_t hb;
-  whmc_status get(const char* name, int idx, double** p) {
-    void* v;
-    WHMC_TRY(workspace(c, std::string(name) + std::to_string(idx), hb, &v));
-    *p = (double*)v;
-    return WHMC_OK;
-  }
-};
-
-// out = sum_{n<=N} coef[n] K^n v  (Horner); tmp_e, tmp_o scratch
-static whmc_status poly_K(whmc_ctx* c, double* out, const double* v, const std::vector<double>& coef, double kappa,
-                          double* tmp_e, double* tmp_o) {
+// out = sum_{n<=N} coef[n] K^n v (K^dag for dagger), Horner; tmp_e, tmp_o scratch
+whmc_status poly_K(whmc_ctx* c, double* out, const double* v, const std::vector<double>& coef, double kappa,
+                   double* tmp_e, double* tmp_o, int dagger) {
   const int N = (int)coef.size() - 1;
   WHMC_TRY(zero_bytes(c, out, (size_t)c->Vh * 192));
   WHMC_TRY(axpby_f64(c, out, coef[N], v, 0.0, 1));
   for (int n = N - 1; n >= 0; --n) {
     WHMC_TRY(copy_f64(c, tmp_o, out, 1));
-    WHMC_TRY(apply_K_f64(c, out, tmp_o, kappa, 0, tmp_e, v, coef[n]));
+    WHMC_TRY(apply_K_f64(c, out, tmp_o, kappa, dagger, tmp_e, v, coef[n]));
   }
   return WHMC_OK;
 }
 
 // s = A^{-1} rhs with A = M_oo^dag M_oo; accumulates statistics
-struct SolveLog {
-  long long iters = 0;
-  int n = 0;
-};
-
-static whmc_status solve(whmc_ctx* c, double* x, const double* rhs, double kappa, const whmc_cg_params* p,
-                         SolveLog* log) {
+whmc_status solve(whmc_ctx* c, double* x, const double* rhs, double kappa, const whmc_cg_params* p, SolveLog* log) {
   whmc_cg_stats st{};
   whmc_status rc = cg_solve(c, x, rhs, &kappa, 1, p, &st);
   if (log) {
@@ -132,9 +115,10 @@ static whmc_status solve2(whmc_ctx* c, double* x, const double* rhs, double kapp
   return rc;
 }
 
-// M~^{-1} phi truncated at N, into out
-static whmc_status filtered_inverse(whmc_ctx* c, double* out, const double* phi, const whmc_filter* f, double kappa,
-                                    const whmc_cg_params* sp, SolveLog* log) {
+// out = (sum_n b_n K^n + alpha M_oo^{-1}) phi; trailing zero coefficients are skipped and
+// alpha = 0 needs no solve
+whmc_status series_inverse(whmc_ctx* c, double* out, const double* phi, std::vector<double> b, double alpha,
+                           double kappa, const whmc_cg_params* sp, SolveLog* log) {
   Fields F{c, (size_t)c->Vh * 192};
   double *te, *to, *g5phi, *s3, *tmp;
   WHMC_TRY(F.get("fi_te", 0, &te));
@@ -142,20 +126,30 @@ static whmc_status filtered_inverse(whmc_ctx* c, double* out, const double* phi,
   WHMC_TRY(F.get("fi_g5phi", 0, &g5phi));
   WHMC_TRY(F.get("fi_s3", 0, &s3));
   WHMC_TRY(F.get("fi_tmp", 0, &tmp));
+  while (b.size() > 1 && b.back() == 0.0) b.pop_back();
+  const bool poly = b.size() > 1 || b[0] != 0.0;
+  if (alpha != 0.0) {
+    WHMC_TRY(gamma5_f64(c, g5phi, phi, 1));
+    WHMC_TRY(solve(c, s3, g5phi, kappa, sp, log));
+    // M_oo^{-1} phi = M_oo^dag gamma_5 s3
+    WHMC_TRY(gamma5_f64(c, tmp, s3, 1));
+    WHMC_TRY(apply_Moo_f64(c, poly ? to : out, tmp, kappa, 1, te));
+  }
+  if (!poly) {
+    if (alpha == 0.0) return zero_bytes(c, out, (size_t)c->Vh * 192);
+    return alpha == 1.0 ? WHMC_OK : axpby_f64(c, out, 0.0, tmp, alpha, 1);
+  }
+  WHMC_TRY(poly_K(c, out, phi, b, kappa, te, tmp, 0));
+  return alpha == 0.0 ? WHMC_OK : axpby_f64(c, out, alpha, to, 1.0, 1);
+}
+
+// M~^{-1} phi truncated at n_max, into out
+static whmc_status filtered_inverse(whmc_ctx* c, double* out, const double* phi, const whmc_filter* f, double kappa,
+                                    const whmc_cg_params* sp, SolveLog* log) {
   std::vector<double> b, cc;
   double alpha;
-  coefficients(f->k, f->n_max, b, cc, alpha);
-  WHMC_TRY(gamma5_f64(c, g5phi, phi, 1));
-  WHMC_TRY(solve(c, s3, g5phi, kappa, sp, log));
-  // M_oo^{-1} phi = M_oo^dag gamma_5 s3
-  WHMC_TRY(gamma5_f64(c, tmp, s3, 1));
-  if (f->k == 0) {
-    WHMC_TRY(apply_Moo_f64(c, out, tmp, kappa, 1, te));
-    return WHMC_OK;
-  }
-  WHMC_TRY(apply_Moo_f64(c, to, tmp, kappa, 1, te));
-  WHMC_TRY(poly_K(c, out, phi, b, kappa, te, tmp));
-  return axpby_f64(c, out, alpha, to, 1.0, 1);
+  coefficients(f->k, f->k == 0 ? 0 : f->n_max, b, cc, alpha);
+  return series_inverse(c, out, phi, b, alpha, kappa, sp, log);
 }
 
 whmc_status pf_action(whmc_ctx* c, const double* phi, const whmc_filter* f, double kappa, const whmc_cg_params* sp,
@@ -168,14 +162,13 @@ whmc_status pf_action(whmc_ctx* c, const double* phi, const whmc_filter* f, doub
   return read_scalar(c, c->red.result + 7, S);
 }
 
-// pseudo-fermion force; out = (acc ? out : 0) - scale_kappa * ..., i.e. F scaled by `scale`
-whmc_status pf_force(whmc_ctx* c, double* out, const double* phi, const whmc_filter* f, double kappa,
-                     const whmc_cg_params* sp, double scale, int accumulate, SolveLog* log) {
+// Force of S = |(sum_{n<=nt} b_n K^n + alpha M_oo^{-1}) phi|^2, scaled by `scale` and added to out
+// (accumulate) or stored.  alpha = 0 (a polynomial action) needs no solve and has no (X~, Y~)
+// pair; b_0 alone (nt = 0) carries no K and no force of its own.
+whmc_status series_force(whmc_ctx* c, double* out, const double* phi, const std::vector<double>& b, double alpha,
+                         double kappa, const whmc_cg_params* sp, double scale, int accumulate, SolveLog* log) {
   Fields F{c, (size_t)c->Vh * 192};
-  const int nt = f->k == 0 ? 0 : f->n_t;   // k = 0: plain action, no polynomial part
-  std::vector<double> b, cc;
-  double alpha;
-  coefficients(f->k, nt, b, cc, alpha);
+  const int nt = (int)b.size() - 1;
   double *te, *to, *rhs2, *sol2, *Yt, *Yte, *Xt, *Xte, *tmp;
   WHMC_TRY(F.get("ff_te", 0, &te));
   WHMC_TRY(F.get("ff_to", 0, &to));
@@ -198,10 +191,11 @@ whmc_status pf_force(whmc_ctx* c, double* out, const double* phi, const whmc_fil
     WHMC_TRY(F.get("ff_X", i, &X[i]));
     WHMC_TRY(F.get("ff_Xe", i, &Xe[i]));
   }
-  const bool filt = f->k >= 1;
+  const bool poly = nt >= 1 || b[0] != 0.0;
+  const bool inv = alpha != 0.0;
   double* Y0 = rhs2;                       // first rhs of the batched solve
   double* g5phi = rhs2 + (size_t)c->Vh * 24;
-  if (filt) {
+  if (poly) {
     // Horner: Y_nt = b_nt phi; Y_{i-1} = b_{i-1} phi + K Y_i  (Ye[i] = H_eo Y_i)
     double* top = nt >= 1 ? Y[nt] : Y0;
     WHMC_TRY(zero_bytes(c, top, F.hb));
@@ -209,32 +203,39 @@ whmc_status pf_force(whmc_ctx* c, double* out, const double* phi, const whmc_fil
     for (int i = nt; i >= 1; --i)
       WHMC_TRY(apply_K_f64(c, i == 1 ? Y0 : Y[i - 1], Y[i], kappa, 0, Ye[i], phi, b[i - 1]));
   }
-  WHMC_TRY(gamma5_f64(c, g5phi, phi, 1));
-  double* s2 = sol2;
-  double* s3 = sol2 + (size_t)c->Vh * 24;
-  if (filt) {
-    WHMC_TRY(solve2(c, sol2, rhs2, kappa, sp, log));
-  } else {
-    WHMC_TRY(solve(c, s3, g5phi, kappa, sp, log));
+  std::vector<const double*> pXe, pXo, pYe, pYo;
+  if (inv) {
+    WHMC_TRY(gamma5_f64(c, g5phi, phi, 1));
+    double* s2 = sol2;
+    double* s3 = sol2 + (size_t)c->Vh * 24;
+    if (poly) {
+      WHMC_TRY(solve2(c, sol2, rhs2, kappa, sp, log));
+    } else {
+      WHMC_TRY(solve(c, s3, g5phi, kappa, sp, log));
+    }
+    // Y~ = alpha M_oo^dag g5 s3 ;  X~ = M_oo s2 + alpha g5 s3
+    WHMC_TRY(gamma5_f64(c, tmp, s3, 1));
+    WHMC_TRY(apply_Moo_f64(c, Yt, tmp, kappa, 1, te));
+    if (alpha != 1.0) WHMC_TRY(axpby_f64(c, Yt, 0.0, tmp, alpha, 1));     // Yt = alpha * Yt
+    if (poly) {
+      WHMC_TRY(apply_Moo_f64(c, Xt, s2, kappa, 0, te));
+      WHMC_TRY(axpby_f64(c, Xt, alpha, tmp, 1.0, 1));
+    } else {
+      WHMC_TRY(copy_f64(c, Xt, tmp, 1));
+      if (alpha != 1.0) WHMC_TRY(axpby_f64(c, Xt, 0.0, tmp, alpha, 1));
+    }
+    // even halves of the (X~, Y~) pair
+    WHMC_TRY(hop(c, WHMC_F64, WHMC_L18, 0, 0, Yte, Yt, nullptr, 0.0, 1.0, nullptr));
+    WHMC_TRY(hop(c, WHMC_F64, WHMC_L18, 0, 1, Xte, Xt, nullptr, 0.0, 1.0, nullptr));
+    pXe.push_back(Xte);
+    pXo.push_back(Xt);
+    pYe.push_back(Yte);
+    pYo.push_back(Yt);
   }
-  // Y~ = alpha M_oo^dag g5 s3 ;  X~ = M_oo s2 + alpha g5 s3
-  WHMC_TRY(gamma5_f64(c, tmp, s3, 1));
-  WHMC_TRY(apply_Moo_f64(c, Yt, tmp, kappa, 1, te));
-  if (alpha != 1.0) WHMC_TRY(axpby_f64(c, Yt, 0.0, tmp, alpha, 1));     // Yt = alpha * Yt
-  if (filt) {
-    WHMC_TRY(apply_Moo_f64(c, Xt, s2, kappa, 0, te));
-    WHMC_TRY(axpby_f64(c, Xt, alpha, tmp, 1.0, 1));
-  } else {
-    WHMC_TRY(copy_f64(c, Xt, tmp, 1));
-  }
-  // even halves of the (X~, Y~) pair
-  WHMC_TRY(hop(c, WHMC_F64, WHMC_L18, 0, 0, Yte, Yt, nullptr, 0.0, 1.0, nullptr));
-  WHMC_TRY(hop(c, WHMC_F64, WHMC_L18, 0, 1, Xte, Xt, nullptr, 0.0, 1.0, nullptr));
-  std::vector<const double*> pXe{Xte}, pXo{Xt}, pYe{Yte}, pYo{Yt};
   if (nt >= 1) {
     // X_1 = Y_0 + Y~;  X_{i+1} = K^dag X_i with Xe[i] = (H^dag)_eo X_i
     WHMC_TRY(copy_f64(c, X[1], Y0, 1));
-    WHMC_TRY(axpby_f64(c, X[1], 1.0, Yt, 1.0, 1));
+    if (inv) WHMC_TRY(axpby_f64(c, X[1], 1.0, Yt, 1.0, 1));
     for (int i = 1; i < nt; ++i) WHMC_TRY(apply_K_f64(c, X[i + 1], X[i], kappa, 1, Xe[i], nullptr, 0.0));
     WHMC_TRY(hop(c, WHMC_F64, WHMC_L18, 0, 1, Xe[nt], X[nt], nullptr, 0.0, 1.0, nullptr));
     for (int i = 1; i <= nt; ++i) {
@@ -244,8 +245,22 @@ whmc_status pf_force(whmc_ctx* c, double* out, const double* phi, const whmc_fil
       pYo.push_back(Y[i]);
     }
   }
+  if (pXe.empty()) {
+    if (!accumulate) WHMC_TRY(zero_bytes(c, out, (size_t)c->Vh * 64 * sizeof(double)));
+    return WHMC_OK;
+  }
   return pf_force_pairs(c, out, pXe.data(), pXo.data(), pYe.data(), pYo.data(), (int)pXe.size(),
                         scale * kappa * kappa, accumulate);
+}
+
+// pseudo-fermion force of the kappa^(2k) filtered action; out = (acc ? out : 0) + scale F
+whmc_status pf_force(whmc_ctx* c, double* out, const double* phi, const whmc_filter* f, double kappa,
+                     const whmc_cg_params* sp, double scale, int accumulate, SolveLog* log) {
+  const int nt = f->k == 0 ? 0 : f->n_t;   // k = 0: plain action, no polynomial part
+  std::vector<double> b, cc;
+  double alpha;
+  coefficients(f->k, nt, b, cc, alpha);
+  return series_force(c, out, phi, b, alpha, kappa, sp, scale, accumulate, log);
 }
 
 whmc_status heatbath(whmc_ctx* c, double* phi, const double* eta, const whmc_filter* f, double kappa) {
@@ -257,63 +272,75 @@ whmc_status heatbath(whmc_ctx* c, double* phi, const double* eta, const whmc_fil
   std::vector<double> b, cc;
   double alpha;
   coefficients(f->k, f->k == 0 ? 0 : f->n_max, b, cc, alpha);
-  WHMC_TRY(poly_K(c, tmp, eta, cc, kappa, te, to));
+  WHMC_TRY(poly_K(c, tmp, eta, cc, kappa, te, to, 0));
   return apply_Moo_f64(c, phi, tmp, kappa, 0, te);
 }
 
 // ------------------------------------------------------------------ HMC
-struct MD {
+namespace {
+// Sexton-Weingarten nesting (Sec. 1): level 0 has the T steps between its P steps, one (half)
+// step of level l >= 1 holds lv[l].nsub steps of level l - 1.  P steps are queued per level and
+// applied before the next T step, so consecutive P steps on the same field cost one force.
+struct MDRun {
   whmc_ctx* c;
-  const whmc_hmc_params* p;
   double* pi;
-  const double* phi;
-  SolveLog log;
-  double pending[2] = {0.0, 0.0};   // P steps not yet applied (merged until the next T step)
+  const std::vector<MDLevel>& lv;
+  int integrator;
+  double lambda;
+  std::vector<double> pending;
 
   whmc_status flush() {
-    if (pending[0] != 0.0) {
-      const double beff = p->beta + delta_beta(p->kappa, p->filter.k);
-      WHMC_TRY(gauge_force(c, pi, beff, -pending[0], 1));
-      pending[0] = 0.0;
-    }
-    if (pending[1] != 0.0) {
-      WHMC_TRY(pf_force(c, pi, phi, &p->filter, p->kappa, &p->md_solver, -pending[1], 1, &log));
-      pending[1] = 0.0;
-    }
+    for (size_t l = 0; l < lv.size(); ++l)
+      if (pending[l] != 0.0) {
+        WHMC_TRY(lv[l].force(-pending[l]));
+        pending[l] = 0.0;
+      }
     return WHMC_OK;
   }
-  void P(int level, double eps) { pending[level] += eps; }
   whmc_status T(double eps) {
     WHMC_TRY(flush());
     return link_update(c, pi, eps);
   }
   whmc_status sub(int level, double span) {
     if (level == 0) return T(span);
-    const int n = p->m0;
+    const int n = lv[level].nsub;
     for (int k = 0; k < n; ++k) WHMC_TRY(run(level - 1, span / n));
     return WHMC_OK;
   }
   whmc_status run(int level, double eps) {
-    if (p->integrator == WHMC_OMELYAN) {
-      const double lam = p->lambda;
-      P(level, lam * eps);
+    if (integrator == WHMC_OMELYAN) {
+      pending[level] += lambda * eps;
       WHMC_TRY(sub(level, eps / 2));
-      P(level, (1 - 2 * lam) * eps);
+      pending[level] += (1 - 2 * lambda) * eps;
       WHMC_TRY(sub(level, eps / 2));
-      P(level, lam * eps);
+      pending[level] += lambda * eps;
     } else {
-      P(level, eps / 2);
+      pending[level] += eps / 2;
       WHMC_TRY(sub(level, eps));
-      P(level, eps / 2);
+      pending[level] += eps / 2;
     }
     return WHMC_OK;
   }
-  whmc_status integrate() {
-    const double eps = p->tau / p->m;
-    for (int k = 0; k < p->m; ++k) WHMC_TRY(run(1, eps));
-    return flush();
-  }
 };
+}  // namespace
+
+whmc_status md_levels(whmc_ctx* c, double* pi, const std::vector<MDLevel>& lv, int integrator, double lambda,
+                      double tau, int m) {
+  MDRun r{c, pi, lv, integrator, lambda, std::vector<double>(lv.size(), 0.0)};
+  const int top = (int)lv.size() - 1;
+  for (int k = 0; k < m; ++k) WHMC_TRY(r.run(top, tau / m));
+  return r.flush();
+}
+
+// gauge action on level 0, the filtered pseudo-fermion action on level 1
+static whmc_status filter_md(whmc_ctx* c, const whmc_hmc_params* p, double* pi, const double* phi, SolveLog* log) {
+  const double beff = p->beta + delta_beta(p->kappa, p->filter.k);
+  std::vector<MDLevel> lv(2);
+  lv[0].force = [=](double s) { return gauge_force(c, pi, beff, s, 1); };
+  lv[1].force = [=](double s) { return pf_force(c, pi, phi, &p->filter, p->kappa, &p->md_solver, s, 1, log); };
+  lv[1].nsub = p->m0;
+  return md_levels(c, pi, lv, p->integrator, p->lambda, p->tau, p->m);
+}
 
 static whmc_status check_hmc(const whmc_hmc_params* p) {
   WHMC_CHECK(p, WHMC_EARG, "null hmc params");
@@ -408,8 +435,7 @@ whmc_status whmc_md_integrate(whmc_ctx* c, const whmc_hmc_params* p, double* pi,
   WHMC_CHECK(c && pi && phi, WHMC_EARG, "whmc_md_integrate: null argument");
   WHMC_TRY(check_hmc(p));
   WHMC_CHECK(c->gauge_loaded, WHMC_ESTATE, "no gauge field loaded");
-  MD md{c, p, pi, phi};
-  WHMC_TRY(md.integrate());
+  WHMC_TRY(filter_md(c, p, pi, phi, nullptr));
   WHMC_HIP(hipStreamSynchronize(c->stream));
   return WHMC_OK;
 }
@@ -432,8 +458,8 @@ whmc_status whmc_hmc_trajectory(whmc_ctx* c, const whmc_hmc_params* p, const dou
   SolveLog log;
   double H0, H1;
   WHMC_TRY(hamiltonian(c, p, (double*)pi, (double*)phi, &H0, &log));
-  MD md{c, p, (double*)pi, (const double*)phi};
-  WHMC_TRY(md.integrate());
+  SolveLog mdlog;
+  WHMC_TRY(filter_md(c, p, (double*)pi, (const double*)phi, &mdlog));
   WHMC_TRY(hamiltonian(c, p, (double*)pi, (double*)phi, &H1, &log));
   const double dH = H1 - H0;
   const bool acc = u < std::exp(-dH);
@@ -448,8 +474,9 @@ whmc_status whmc_hmc_trajectory(whmc_ctx* c, const whmc_hmc_params* p, const dou
   res->H1 = H1;
   res->accepted = acc ? 1 : 0;
   res->plaquette = plaq / (18.0 * (double)c->V);
-  res->cg_iters = log.iters + md.log.iters;
-  res->n_solves = log.n + md.log.n;
+  res->cg_iters = log.iters + mdlog.iters;
+  res->n_solves = log.n + mdlog.n;
+  res->poly_iters = 0;
   res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return WHMC_OK;
 }

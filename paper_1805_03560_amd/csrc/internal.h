@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -133,8 +134,6 @@ whmc_status apply_K_f64(whmc_ctx* c, double* out, const double* in, double kappa
 whmc_status cg_solve(whmc_ctx* c, double* x, const double* b, const double* kappas, int nrhs,
                      const whmc_cg_params* p, whmc_cg_stats* st);
 
-// ---- multi-RHS (multi.hip)
-
 // ---- gauge and force kernels (gauge.hip)
 whmc_status plaquette_sum(whmc_ctx* c, double* host_out);
 whmc_status gauge_force(whmc_ctx* c, double* F, double beta_eff, double scale, int accumulate);
@@ -145,5 +144,38 @@ whmc_status mom_update(whmc_ctx* c, double* pi, const double* F, double eps);   
 whmc_status link_update(whmc_ctx* c, const double* pi, double eps);              // U = exp(eps pi) U
 whmc_status algebra_norm2(whmc_ctx* c, const double* pi, double* host_out);
 whmc_status pack_algebra(whmc_ctx* c, double* dst, const double* src, int unpack);
+
+// ---- actions, forces and molecular dynamics (hmc.hip)
+// named odd-site FP64 scratch fields of the context
+struct Fields {
+  whmc_ctx* c;
+  size_t hb;
+  whmc_status get(const char* name, int idx, double** p) {
+    void* v;
+    WHMC_TRY(workspace(c, std::string(name) + std::to_string(idx), hb, &v));
+    *p = (double*)v;
+    return WHMC_OK;
+  }
+};
+struct SolveLog {   // M_oo^dag M_oo solver statistics of one action / force / trajectory
+  long long iters = 0;
+  int n = 0;
+};
+struct MDLevel {    // one Sexton-Weingarten level: pi += scale F_l, and its substep count
+  std::function<whmc_status(double scale)> force;
+  int nsub = 0;
+};
+double delta_beta(double kappa, int k);
+whmc_cg_params default_solver();
+whmc_status solve(whmc_ctx* c, double* x, const double* rhs, double kappa, const whmc_cg_params* p, SolveLog* log);
+whmc_status poly_K(whmc_ctx* c, double* out, const double* v, const std::vector<double>& coef, double kappa,
+                   double* tmp_e, double* tmp_o, int dagger);
+whmc_status series_inverse(whmc_ctx* c, double* out, const double* phi, std::vector<double> b, double alpha,
+                           double kappa, const whmc_cg_params* sp, SolveLog* log);
+whmc_status series_force(whmc_ctx* c, double* out, const double* phi, const std::vector<double>& b, double alpha,
+                         double kappa, const whmc_cg_params* sp, double scale, int accumulate, SolveLog* log);
+whmc_status heatbath(whmc_ctx* c, double* phi, const double* eta, const whmc_filter* f, double kappa);
+whmc_status md_levels(whmc_ctx* c, double* pi, const std::vector<MDLevel>& lv, int integrator, double lambda,
+                      double tau, int m);
 
 }  // namespace whmc

@@ -57,10 +57,34 @@ class HMCParams(ctypes.Structure):
 class TrajResult(ctypes.Structure):
     _fields_ = [("dH", ctypes.c_double), ("H0", ctypes.c_double), ("H1", ctypes.c_double),
                 ("accepted", ctypes.c_int), ("plaquette", ctypes.c_double), ("cg_iters", ctypes.c_longlong),
-                ("n_solves", ctypes.c_int), ("seconds", ctypes.c_double)]
+                ("n_solves", ctypes.c_int), ("seconds", ctypes.c_double), ("poly_iters", ctypes.c_longlong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+MAX_POLY = 4
+
+
+class Rooted(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("jmax", ctypes.c_int), ("n", ctypes.c_int * MAX_POLY), ("k", ctypes.c_int),
+                ("n_t", ctypes.c_int), ("n_max", ctypes.c_int)]
+
+
+class RootedHMCParams(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("kappa", ctypes.c_double), ("rooted", Rooted),
+                ("integrator", ctypes.c_int), ("lam", ctypes.c_double), ("m", ctypes.c_int),
+                ("msub", ctypes.c_int * (MAX_POLY + 1)), ("tau", ctypes.c_double), ("md_solver", CGParams),
+                ("action_solver", CGParams), ("heatbath_solver", CGParams)]
+
+
+def rooted(N, ns, k=0, n_t=0, n_max=0):
+    """rooted-polynomial action (Sec. 2.1): root order N, degrees ns = (n_1, ..., n_jmax)."""
+    ns = [int(v) for v in ns]
+    if len(ns) > MAX_POLY:
+        raise ValueError(f"at most {MAX_POLY} polynomials")
+    return Rooted(int(N), len(ns), (ctypes.c_int * MAX_POLY)(*(ns + [0] * (MAX_POLY - len(ns)))), int(k), int(n_t),
+                  int(n_max))
 
 
 def cg_params(tol=1e-10, maxiter=10000, prec=F64, links=L18, delta=0.1, check_every=8, rhs_block=0, rhs_lanes=0):
@@ -110,6 +134,20 @@ _SIGS = {
                             ctypes.c_int),
     "whmc_md_integrate": ([_P, ctypes.POINTER(HMCParams), _P, _P], ctypes.c_int),
     "whmc_hamiltonian": ([_P, ctypes.POINTER(HMCParams), _P, _P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "whmc_rooted_coefficients": ([ctypes.POINTER(Rooted), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.POINTER(ctypes.c_double)],
+                                 ctypes.c_int),
+    "whmc_rooted_heatbath": ([_P, _P, _P, ctypes.POINTER(Rooted), ctypes.c_double, ctypes.POINTER(CGParams),
+                              ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
+    "whmc_rooted_action": ([_P, ctypes.POINTER(ctypes.c_double), _P, ctypes.POINTER(Rooted), ctypes.c_double,
+                            ctypes.POINTER(CGParams)], ctypes.c_int),
+    "whmc_rooted_force": ([_P, _P, _P, ctypes.POINTER(Rooted), ctypes.c_int, ctypes.c_double,
+                           ctypes.POINTER(CGParams), ctypes.c_int], ctypes.c_int),
+    "whmc_rooted_trajectory": ([_P, ctypes.POINTER(RootedHMCParams), _P, _P, ctypes.c_double,
+                                ctypes.POINTER(TrajResult)], ctypes.c_int),
+    "whmc_rooted_md_integrate": ([_P, ctypes.POINTER(RootedHMCParams), _P, _P], ctypes.c_int),
+    "whmc_rooted_hamiltonian": ([_P, ctypes.POINTER(RootedHMCParams), _P, _P, ctypes.POINTER(ctypes.c_double)],
+                                ctypes.c_int),
 }
 
 
@@ -147,6 +185,20 @@ def filter_coefficients(k, n):
     a = ctypes.c_double()
     _check(lib().whmc_filter_coefficients(k, n, b, c, ctypes.byref(a)))
     return list(b), list(c), a.value
+
+
+def rooted_coefficients(r, nb):
+    """([p_1, ..., p_jmax], b[0..nb], alpha) of the rooted action r, computed by the library."""
+    ns = [r.n[j] for j in range(r.jmax)]
+    p = (ctypes.c_double * max(1, sum(n + 1 for n in ns)))()
+    b = (ctypes.c_double * (nb + 1))()
+    a = ctypes.c_double()
+    _check(lib().whmc_rooted_coefficients(ctypes.byref(r), p, b, int(nb), ctypes.byref(a)))
+    out, o = [], 0
+    for n in ns:
+        out.append(list(p[o:o + n + 1]))
+        o += n + 1
+    return out, list(b), a.value
 
 
 class Context:
@@ -350,6 +402,55 @@ class Context:
         h = ctypes.c_double()
         _check(lib().whmc_hamiltonian(self._h, ctypes.byref(params), _ptr(pi), _ptr(phi), ctypes.byref(h)))
         return h.value
+
+    # ------------------------------------------------------------ rooted polynomials (Sec. 2.1)
+    def rooted_heatbath(self, eta, r, kappa, solver=None):
+        """(phi, iterations): the jmax*N + 1 fields of the rooted action from the sources eta."""
+        phi = torch.empty_like(eta)
+        it = ctypes.c_longlong()
+        _check(lib().whmc_rooted_heatbath(self._h, _ptr(phi), _ptr(eta), ctypes.byref(r), float(kappa),
+                                          ctypes.byref(solver) if solver is not None else None, ctypes.byref(it)))
+        return phi, it.value
+
+    def rooted_action(self, phi, r, kappa, solver=None):
+        """[S_1, ..., S_jmax, S_r]"""
+        S = (ctypes.c_double * (r.jmax + 1))()
+        _check(lib().whmc_rooted_action(self._h, S, _ptr(phi), ctypes.byref(r), float(kappa),
+                                        ctypes.byref(solver) if solver is not None else None))
+        return list(S)
+
+    def rooted_force(self, phi, r, kappa, term=0, solver=None, out=None, accumulate=False):
+        out = self.algebra() if out is None else out
+        _check(lib().whmc_rooted_force(self._h, _ptr(out), _ptr(phi), ctypes.byref(r), int(term), float(kappa),
+                                       ctypes.byref(solver) if solver is not None else None,
+                                       FORCE_ACCUMULATE if accumulate else 0))
+        return out
+
+    def rooted_trajectory(self, params, pi0, eta, u):
+        res = TrajResult()
+        _check(lib().whmc_rooted_trajectory(self._h, ctypes.byref(params), _ptr(pi0), _ptr(eta), float(u),
+                                            ctypes.byref(res)))
+        return res.as_dict()
+
+    def rooted_md_integrate(self, params, pi, phi):
+        _check(lib().whmc_rooted_md_integrate(self._h, ctypes.byref(params), _ptr(pi), _ptr(phi)))
+        return pi
+
+    def rooted_hamiltonian(self, params, pi, phi):
+        h = ctypes.c_double()
+        _check(lib().whmc_rooted_hamiltonian(self._h, ctypes.byref(params), _ptr(pi), _ptr(phi), ctypes.byref(h)))
+        return h.value
+
+
+def rooted_hmc_params(beta=5.6, kappa=0.1575, rooted_action=None, integrator=LEAPFROG, lam=1.0 / 6.0, m=5,
+                      msub=(6, 5, 4), tau=1.4142135623730951, md_solver=None, action_solver=None,
+                      heatbath_solver=None):
+    """multi-level HMC with the rooted action; msub = (m_0, m_1, ..., m_jmax) as in Sec. 4.2."""
+    ms = [int(v) for v in msub]
+    ms = ms + [1] * (MAX_POLY + 1 - len(ms))
+    return RootedHMCParams(beta, kappa, rooted_action, integrator, lam, m, (ctypes.c_int * (MAX_POLY + 1))(*ms), tau,
+                           md_solver or cg_params(tol=1e-12), action_solver or cg_params(tol=1e-12),
+                           heatbath_solver or cg_params(tol=1e-12))
 
 
 def hmc_params(beta=5.6, kappa=0.156, k=0, n_t=0, n_max=0, integrator=OMELYAN, lam=1.0 / 6.0, m=10, m0=4, tau=1.0,

@@ -46,3 +46,38 @@ def test_filter_coefficients_match_oracle(k, n):
 def test_filter_coefficients_reject_bad_input():
     with pytest.raises(whmc.WhmcError):
         whmc.filter_coefficients(-1, 3)
+
+
+@pytest.mark.parametrize("N,ns,k,nb", [(2, (8, 32), 0, 300), (4, (8, 32), 0, 260), (16, (8, 32), 0, 200),
+                                       (8, (16, 42), 2, 260), (3, (5,), 1, 80), (2, (3, 7, 15, 31), 0, 120)])
+def test_rooted_coefficients_match_oracle(N, ns, k, nb):
+    """p_j, b_n and alpha of eq. (restM) from the library's long-double series against the
+    oracle's exact rational arithmetic (whose alpha column is pinned to Table RunPoly1)."""
+    from oracle import rooted
+    r = whmc.rooted(N, ns, k=k)
+    p, b, alpha = whmc.rooted_coefficients(r, nb)
+    po = rooted.polynomials(N, ns, k)
+    bo = rooted.remainder_b(N, ns, k, nb)
+    assert alpha == pytest.approx(float(rooted.alpha(N, ns, k)), rel=1e-15)
+    for pj, pjo in zip(p, po):
+        assert len(pj) == len(pjo)
+        np.testing.assert_allclose(pj, [float(v) for v in pjo], rtol=1e-15, atol=1e-19)
+    np.testing.assert_allclose(b, [float(v) for v in bo], rtol=0, atol=1e-16)
+
+
+def test_rooted_coefficients_without_polynomials_are_the_filter():
+    """jmax = 0 leaves M_1 = M~ itself: b_n and alpha are the kappa^(2k) filter's."""
+    for k in (0, 1, 2):
+        _, b, alpha = whmc.rooted_coefficients(whmc.rooted(4, (), k=k), 40)
+        bf, _, af = whmc.filter_coefficients(k, 40)
+        assert alpha == pytest.approx(af, rel=1e-15)
+        np.testing.assert_allclose(b, bf, rtol=0, atol=1e-17)
+
+
+def test_rooted_coefficients_reject_bad_input():
+    for r in (whmc.rooted(0, (8,)), whmc.rooted(2, (0,)), whmc.rooted(2, (8,), k=3),
+              whmc.rooted(2, (8,), n_t=1001)):
+        with pytest.raises(whmc.WhmcError):
+            whmc.rooted_coefficients(r, 10)
+    with pytest.raises(whmc.WhmcError):
+        whmc.rooted_coefficients(whmc.rooted(2, (8,)), 1001)

@@ -1,0 +1,177 @@
+"""GPU parity of the rooted-polynomial action (Sec. 2.1) against the oracle, through the C ABI.
+
+Heat bath, the terms of the action, the force of every term, the multi-level trajectory, and
+jmax = 0 against the filter trajectory.  Tolerances: polynomial applications are plain FP64
+stencil sums (1e-12 relative); the polynomial heat bath and the remainder's M_oo^{-1} are solves
+run to 1e-14 on both sides, so they agree to cond x 1e-14 (1e-10 allowed)."""
+import numpy as np
+import pytest
+
+from oracle import hmc, rooted
+from oracle.lattice import Lattice
+from paper_1805_03560_amd import synth, whmc
+
+from gpu_util import algebra_to_numpy, make_ctx, pack_half, rel_err, to_dev, unpack_half
+
+pytestmark = pytest.mark.gpu
+
+SOLVER = whmc.cg_params(tol=1e-14, check_every=4)
+
+
+def _sources(lat, n, seed):
+    return np.stack([synth.gaussian_spinor(lat.Vh, seed + f) for f in range(n)])
+
+
+# (N, ns, k, n_t, n_max): no filter / kappa^4 with one polynomial / kappa^2 with three polynomials
+CASES = [(2, (4, 10), 0, 20, 40), (3, (3,), 2, 12, 40), (1, (2, 5, 9), 1, 8, 25)]
+
+
+@pytest.mark.parametrize("N,ns,k,n_t,n_max", CASES)
+@pytest.mark.parametrize("dims,gen,kappa", [((4, 4, 4, 4), "haar", 0.156), ((4, 2, 2, 8), "smooth", 0.12)])
+def test_rooted_heatbath_action_force_parity(N, ns, k, n_t, n_max, dims, gen, kappa):
+    lat = Lattice(dims)
+    U = synth.haar_links(dims, 4000) if gen == "haar" else synth.smooth_links(dims, 4000, width=0.3)
+    p = rooted.RootedHMCParams(kappa=kappa, N=N, ns=ns, k=k, n_t=n_t, n_max=n_max, tol=1e-14)
+    nf = len(ns) * N + 1
+    etas = _sources(lat, nf, 4010)
+    ctx = make_ctx(dims, U)
+    r = whmc.rooted(N, ns, k=k, n_t=n_t, n_max=n_max)
+
+    phis_ref = rooted.rooted_heatbath(lat, U, list(etas), p)
+    phi, iters = ctx.rooted_heatbath(pack_half(ctx, etas), r, kappa, solver=SOLVER)
+    got = unpack_half(ctx, phi, nf)
+    assert iters >= (nf - 1)
+    for f in range(nf - 1):
+        assert rel_err(got[f], phis_ref[f]) < 1e-10, f
+    assert rel_err(got[-1], phis_ref[-1]) < 1e-12
+
+    # actions and forces on the oracle's fields
+    phi_b = pack_half(ctx, np.stack(phis_ref))
+    S = ctx.rooted_action(phi_b, r, kappa, solver=SOLVER)
+    ps, b, al = rooted.coefficients_f64(N, ns, k, max(n_t, n_max))
+    for j, pj in enumerate(ps):
+        ref = sum(rooted.poly_action(lat, U, phis_ref[j * N + i], pj, kappa) for i in range(N))
+        assert S[j] == pytest.approx(ref, rel=1e-12)
+    assert S[-1] == pytest.approx(rooted.remainder_action(lat, U, phis_ref[-1], b[:n_max + 1], al, kappa, 1e-14),
+                                  rel=1e-11)
+    # the heat bath sets every term to the norm of its sources (the remainder up to truncation)
+    for j in range(len(ns)):
+        assert S[j] == pytest.approx(float(np.sum(np.abs(etas[j * N:(j + 1) * N]) ** 2)), rel=1e-9)
+
+    total = None
+    for term in range(1, len(ns) + 2):
+        F = algebra_to_numpy(ctx, ctx.rooted_force(phi_b, r, kappa, term=term, solver=SOLVER))
+        if term <= len(ns):
+            ref = sum(rooted.series_force(lat, U, phis_ref[(term - 1) * N + i], ps[term - 1], 0.0, kappa)
+                      for i in range(N))
+            assert rel_err(F, ref) < 1e-11, term
+        else:
+            ref = rooted.series_force(lat, U, phis_ref[-1], b[:n_t + 1], al, kappa, tol=1e-14)
+            assert rel_err(F, ref) < 1e-10
+        total = ref if total is None else total + ref
+    F = algebra_to_numpy(ctx, ctx.rooted_force(phi_b, r, kappa, term=0, solver=SOLVER))
+    assert rel_err(F, total) < 1e-10
+
+
+def test_rooted_polynomial_force_on_a_sliced_lattice():
+    """time slices of 8 x 128 sites: the per-XCD slice schedule of the stencil and force kernels."""
+    dims = (4, 8, 16, 16)
+    lat = Lattice(dims)
+    U = synth.smooth_links(dims, 4020)
+    kappa, N, ns = 0.13, 2, (3,)
+    phis = _sources(lat, N + 1, 4021)
+    ctx = make_ctx(dims, U)
+    r = whmc.rooted(N, ns, k=0, n_t=4, n_max=4)
+    F = algebra_to_numpy(ctx, ctx.rooted_force(pack_half(ctx, phis), r, kappa, term=1))
+    ps, _, _ = rooted.coefficients_f64(N, ns, 0, 4)
+    ref = sum(rooted.series_force(lat, U, phis[i], ps[0], 0.0, kappa) for i in range(N))
+    assert rel_err(F, ref) < 1e-11
+
+
+def _rooted_wp(p, integrator):
+    return whmc.rooted_hmc_params(beta=p.beta, kappa=p.kappa,
+                                  rooted_action=whmc.rooted(p.N, p.ns, k=p.k, n_t=p.n_t, n_max=p.n_max),
+                                  integrator=integrator, lam=p.lam, m=p.m, msub=p.msub, tau=p.tau,
+                                  md_solver=SOLVER, action_solver=SOLVER, heatbath_solver=SOLVER)
+
+
+@pytest.mark.parametrize("integrator,N,ns,k", [("leapfrog", 2, (3, 6), 0), ("omelyan", 1, (4,), 2)])
+def test_rooted_trajectory_parity(integrator, N, ns, k):
+    dims = (4, 2, 2, 4)
+    lat = Lattice(dims)
+    U = synth.smooth_links(dims, 4030)
+    pi = synth.gaussian_momenta(dims, 4031)
+    p = rooted.RootedHMCParams(kappa=0.13, N=N, ns=ns, k=k, n_t=10, n_max=30, integrator=integrator, m=3,
+                               msub=(2, 2, 2)[:len(ns) + 1], tau=0.5, tol=1e-14)
+    etas = _sources(lat, len(ns) * N + 1, 4032)
+    ref = rooted.rooted_trajectory(lat, U, pi, list(etas), 0.5, p)
+    ctx = make_ctx(dims, U)
+    wp = _rooted_wp(p, whmc.OMELYAN if integrator == "omelyan" else whmc.LEAPFROG)
+    res = ctx.rooted_trajectory(wp, ctx.pack_algebra(to_dev(pi)), pack_half(ctx, etas), 0.5)
+    assert res["H0"] == pytest.approx(ref["H0"], rel=1e-12)
+    assert res["dH"] == pytest.approx(ref["dH"], abs=1e-8)
+    assert bool(res["accepted"]) == ref["accepted"]
+    assert res["poly_iters"] > 0 and res["n_solves"] > 0
+    assert rel_err(ctx.export_gauge().cpu().numpy(), ref["U"]) < 1e-10
+
+
+def test_rooted_md_reversibility_and_dtau_scaling():
+    dims = (4, 4, 4, 4)
+    lat = Lattice(dims)
+    U = synth.smooth_links(dims, 4040)
+    pi0 = synth.gaussian_momenta(dims, 4041)
+    N, ns = 2, (3, 6)
+    etas = _sources(lat, len(ns) * N + 1, 4042)
+    ctx = make_ctx(dims, U)
+    dHs = []
+    for m in (2, 4, 8):
+        p = rooted.RootedHMCParams(kappa=0.15, N=N, ns=ns, k=1, n_t=12, n_max=12, m=m, msub=(2, 1, 1), tau=0.5)
+        wp = _rooted_wp(p, whmc.LEAPFROG)
+        ctx.load_gauge(to_dev(U))
+        phi, _ = ctx.rooted_heatbath(pack_half(ctx, etas), wp.rooted, p.kappa, solver=SOLVER)
+        pi = ctx.pack_algebra(to_dev(pi0))
+        H0 = ctx.rooted_hamiltonian(wp, pi, phi)
+        ctx.rooted_md_integrate(wp, pi, phi)
+        dHs.append(ctx.rooted_hamiltonian(wp, pi, phi) - H0)
+        if m == 4:
+            ctx.rooted_md_integrate(wp, -pi, phi)   # flip momenta and integrate back
+            assert float(np.sum(np.abs(ctx.export_gauge().cpu().numpy() - U) ** 2)) < 1e-20
+    assert 3.0 < dHs[0] / dHs[1] < 5.5 and 3.3 < dHs[1] / dHs[2] < 4.8, dHs
+
+
+def test_rooted_without_polynomials_is_the_filter_trajectory():
+    """jmax = 0 runs the kappa^4 filter: same H0, dH and final field as whmc_hmc_trajectory."""
+    dims = (4, 2, 2, 4)
+    lat = Lattice(dims)
+    U = synth.smooth_links(dims, 4050)
+    pi = synth.gaussian_momenta(dims, 4051)
+    eta = synth.gaussian_spinor(lat.Vh, 4052)
+    ctx = make_ctx(dims, U)
+    fp = whmc.hmc_params(beta=5.6, kappa=0.15, k=2, n_t=6, n_max=29, integrator=whmc.OMELYAN, m=3, m0=2, tau=0.5,
+                         md_solver=SOLVER, action_solver=SOLVER)
+    ref = ctx.hmc_trajectory(fp, ctx.pack_algebra(to_dev(pi)), pack_half(ctx, eta), 0.5)
+    U_ref = ctx.export_gauge().cpu().numpy()
+    ctx.load_gauge(to_dev(U))
+    rp = whmc.rooted_hmc_params(beta=5.6, kappa=0.15, rooted_action=whmc.rooted(5, (), k=2, n_t=6, n_max=29),
+                                integrator=whmc.OMELYAN, m=3, msub=(2,), tau=0.5, md_solver=SOLVER,
+                                action_solver=SOLVER, heatbath_solver=SOLVER)
+    res = ctx.rooted_trajectory(rp, ctx.pack_algebra(to_dev(pi)), pack_half(ctx, eta), 0.5)
+    assert res["H0"] == pytest.approx(ref["H0"], rel=1e-13)
+    assert res["dH"] == pytest.approx(ref["dH"], abs=1e-10)
+    assert res["accepted"] == ref["accepted"] and res["poly_iters"] == 0
+    assert rel_err(ctx.export_gauge().cpu().numpy(), U_ref) < 1e-12
+
+
+def test_rooted_rejects_bad_arguments():
+    dims = (4, 2, 2, 4)
+    lat = Lattice(dims)
+    ctx = make_ctx(dims, synth.smooth_links(dims, 4060))
+    r = whmc.rooted(2, (3,), n_t=4, n_max=4)
+    phi = pack_half(ctx, _sources(lat, 3, 4061))
+    with pytest.raises(whmc.WhmcError):
+        ctx.rooted_force(phi, r, 0.15, term=3)
+    with pytest.raises(whmc.WhmcError):
+        ctx.rooted_action(phi, whmc.rooted(2, (3,), k=3), 0.15)
+    bad = whmc.rooted_hmc_params(rooted_action=r, msub=(0, 1))
+    with pytest.raises(whmc.WhmcError):
+        ctx.rooted_hamiltonian(bad, ctx.algebra(), phi)

@@ -92,3 +92,69 @@ def test_force_is_the_derivative_of_the_action(which):
     h = 1e-4 if which == "poly" else 1e-3
     fd = (8 * (S(shift(h)) - S(shift(-h))) - (S(shift(2 * h)) - S(shift(-2 * h)))) / (12 * h)
     assert float(np.sum(om * F)) == pytest.approx(fd, rel=1e-7 if which == "poly" else 1e-5)
+
+
+# ---------------------------------------------------------------- HMC with the rooted action
+
+def _hmc_setup(seed, p):
+    from oracle import hmc   # noqa: F401  (integrate_levels is shared with the filter HMC)
+    dims = (2, 2, 2, 4)
+    lat = Lattice(dims)
+    U = synth.smooth_links(dims, seed, width=0.3)
+    pi = synth.gaussian_momenta(dims, seed + 1)
+    etas = [synth.gaussian_spinor(lat.Vh, seed + 2 + f) for f in range(len(p.ns) * p.N + 1)]
+    return lat, U, pi, etas
+
+
+def test_rooted_md_is_second_order_in_the_step_size():
+    """n_t = n_max: the force is the derivative of the action in H, so Delta H falls as dtau^2 when
+    every level's step is halved (leapfrog, Sec. 4.2)."""
+    base = rooted.RootedHMCParams(kappa=0.15, N=2, ns=(3, 6), n_t=12, n_max=12, m=2, msub=(1, 1, 2), tau=0.5,
+                                  tol=1e-14)
+    lat, U, pi, etas = _hmc_setup(300, base)
+    phis = rooted.rooted_heatbath(lat, U, etas, base)
+    dHs = []
+    for m in (2, 4, 8):
+        p = rooted.RootedHMCParams(**{**base.__dict__, "m": m})
+        U1, pi1 = rooted.rooted_integrate(lat, U, pi, phis, p)
+        dHs.append(rooted.rooted_hamiltonian(lat, U1, pi1, phis, p) - rooted.rooted_hamiltonian(lat, U, pi, phis, p))
+    r1, r2 = dHs[0] / dHs[1], dHs[1] / dHs[2]
+    assert 3.0 < r1 < 5.5 and 3.5 < r2 < 4.6, dHs
+
+
+def test_rooted_md_is_reversible():
+    p = rooted.RootedHMCParams(kappa=0.15, N=2, ns=(3, 6), k=1, n_t=8, n_max=20, m=2, msub=(2, 1, 2), tau=0.4,
+                               tol=1e-14)
+    lat, U, pi, etas = _hmc_setup(310, p)
+    phis = rooted.rooted_heatbath(lat, U, etas, p)
+    U1, pi1 = rooted.rooted_integrate(lat, U, pi, phis, p)
+    U2, _ = rooted.rooted_integrate(lat, U1, -pi1, phis, p)
+    assert float(np.sum(np.abs(U - U2) ** 2)) < 1e-22
+
+
+def test_rooted_without_polynomials_is_the_filter_hmc():
+    """jmax = 0: one remainder field with the filter's coefficients on level 1 -- the trajectory of
+    the kappa^4 filter (a separate code path: hpe's tail-sum coefficients and filtered action)."""
+    from oracle import hmc
+    p = rooted.RootedHMCParams(kappa=0.15, N=3, ns=(), k=2, n_t=6, n_max=29, integrator="omelyan", m=2,
+                               msub=(2,), tau=0.3, tol=1e-14)
+    lat, U, pi, etas = _hmc_setup(320, p)
+    ref = hmc.trajectory(lat, U, pi, etas[0], 0.5, hmc.HMCParams(beta=p.beta, kappa=p.kappa, k=2, n_t=6, n_max=29,
+                                                                   integrator="omelyan", m=2, m0=2, tau=0.3,
+                                                                   tol=1e-14))
+    res = rooted.rooted_trajectory(lat, U, pi, etas, 0.5, p)
+    assert res["H0"] == pytest.approx(ref["H0"], rel=1e-12)
+    assert res["dH"] == pytest.approx(ref["dH"], rel=1e-8, abs=1e-10)
+    assert np.abs(res["U_end"] - ref["U_end"]).max() < 1e-12
+
+
+def test_rooted_heat_bath_sets_the_action_to_the_source_norm():
+    """after the heat bath, every term of the action equals |eta|^2 of its sources: exact for the
+    polynomial terms, up to the truncation at n_max for the remainder."""
+    p = rooted.RootedHMCParams(kappa=0.15, N=2, ns=(3, 7), k=2, n_max=60, tol=1e-14)
+    lat, U, pi, etas = _hmc_setup(330, p)
+    phis = rooted.rooted_heatbath(lat, U, etas, p)
+    H = rooted.rooted_hamiltonian(lat, U, pi, phis, p)
+    S_G = gauge.gauge_action(lat, U, p.beta + 96 * p.kappa ** 4)
+    eta2 = sum(float(np.vdot(e, e).real) for e in etas)
+    assert H - 0.5 * float(np.sum(pi * pi)) - S_G == pytest.approx(eta2, rel=1e-10)
