@@ -83,7 +83,7 @@ def summarize(records, therm=0):
     out["max_abs_dH"] = float(np.max(np.abs(dh)))
     out["cg_iters_per_traj"] = float(np.mean([r["cg_iters"] for r in recs]))
     out["seconds_per_traj"] = float(np.mean([r["seconds"] for r in recs]))
-    for key in ("F_PF2", "F_G2"):
+    for key in sorted({k for r in recs for k in r if k.startswith("F_") and k.endswith("2")}):
         v = [r[key] for r in recs if key in r]
         if len(v) > 2:
             v = np.asarray(v)

@@ -18,6 +18,13 @@ a resumed run reproduces the uninterrupted one bit for bit.
         --filter 2 15 29 --integrator omelyan --m 6 --m0 4 --tau 1.41421356 --ntraj 500 \\
         --out run_k4 [--resume run_k4/U_last.npy --first 500] [--max-seconds 1000]
 
+With --rooted N n_1 .. n_jmax the pseudo-fermion action is the rooted-polynomial one of Sec. 2.1
+(built on the filter of --filter, whose n_t and n_max then truncate the remainder) on the
+multi-level scheme of Sec. 4.2: --msub m_0 .. m_jmax, --m remainder steps, e.g. the 16^3 x 32 runs
+
+    python -m paper_1805_03560_amd.ensemble --dims 32 16 16 16 --beta 5.6 --kappa 0.1575 \\
+        --filter 0 160 400 --rooted 4 8 32 --msub 6 5 4 --m 5 --integrator leapfrog --out run_N4
+
 Writes <out>/traj.jsonl (one JSON record per trajectory) and <out>/U_last.npy (the gauge field
 after the last trajectory, complex128 (L_t, L_z, L_y, L_x, 4, 3, 3)).
 """
@@ -53,7 +60,12 @@ def parse(argv=None):
     ap.add_argument("--rhs-lanes", type=int, default=2,
                     help="multi-RHS blocking of the two-rhs force solves (fixed, not autotuned, so that runs are "
                          "bitwise reproducible: the blocking sets the summation order of the reductions)")
-    ap.add_argument("--forces", action="store_true", help="record (F,F) of both forces at each start")
+    ap.add_argument("--rooted", type=int, nargs="+", default=None, metavar="N_OR_DEGREE",
+                    help="rooted polynomials: root order N, then the degrees n_1 .. n_jmax (Sec. 2.1)")
+    ap.add_argument("--msub", type=int, nargs="+", default=None,
+                    help="rooted action: m_0 .. m_jmax, steps of level l-1 per step of level l")
+    ap.add_argument("--heatbath-tol", type=float, default=1e-12, help="rooted action: CG on p_j^dag p_j")
+    ap.add_argument("--forces", action="store_true", help="record (F,F) of every force at each start")
     ap.add_argument("--max-seconds", type=float, default=None, help="stop after this much wall time")
     ap.add_argument("--compare-solvers", action="store_true",
                     help="at the end, time BiCGstab on M_oo against CG on the normal equations on the final field")
@@ -126,10 +138,21 @@ def main(argv=None):
     integ = whmc.OMELYAN if a.integrator == "omelyan" else whmc.LEAPFROG
     md = whmc.cg_params(tol=a.md_tol, rhs_block=1, rhs_lanes=a.rhs_lanes)
     act = whmc.cg_params(tol=a.action_tol)
-    p = whmc.hmc_params(beta=a.beta, kappa=a.kappa, k=k, n_t=n_t, n_max=n_max, integrator=integ, lam=a.lam, m=a.m,
-                        m0=a.m0, tau=a.tau, md_solver=md, action_solver=act)
-    n_pi = 64 * Vh    # 2 parities x 4 directions x 8 generators x Vh
-    n_eta = 24 * Vh   # 12 complex components x Vh
+    if a.rooted:
+        r = whmc.rooted(a.rooted[0], a.rooted[1:], k=k, n_t=n_t, n_max=n_max)
+        msub = a.msub or [a.m0] + [1] * r.jmax
+        if len(msub) != r.jmax + 1:
+            raise SystemExit("--msub needs m_0 .. m_jmax (one more value than there are polynomials)")
+        p = whmc.rooted_hmc_params(beta=a.beta, kappa=a.kappa, rooted_action=r, integrator=integ, lam=a.lam, m=a.m,
+                                   msub=msub, tau=a.tau, md_solver=md, action_solver=act,
+                                   heatbath_solver=whmc.cg_params(tol=a.heatbath_tol))
+        n_fields = r.jmax * r.N + 1
+    else:
+        p = whmc.hmc_params(beta=a.beta, kappa=a.kappa, k=k, n_t=n_t, n_max=n_max, integrator=integ, lam=a.lam,
+                            m=a.m, m0=a.m0, tau=a.tau, md_solver=md, action_solver=act)
+        n_fields = 1
+    n_pi = 64 * Vh                # 2 parities x 4 directions x 8 generators x Vh
+    n_eta = 24 * Vh * n_fields    # 12 complex components x Vh per pseudo-fermion field
     log = open(os.path.join(a.out, "traj.jsonl"), "a")
     t_start = time.time()
     done = 0
@@ -137,15 +160,23 @@ def main(argv=None):
         pi, eta, u = draws(torch, dev, a.seed, traj, n_pi, n_eta)
         rec = {"traj": traj}
         if a.forces:
-            phi = ctx.heatbath_phi(eta, k, n_t, n_max, a.kappa)
-            fpf = ctx.force(phi, k, n_t, n_max, a.kappa, a.beta, flags=whmc.FORCE_PF, solver=md)
-            fg = ctx.force(phi, k, n_t, n_max, a.kappa, a.beta, flags=whmc.FORCE_GAUGE)
-            rec["F_PF2"] = float(torch.dot(fpf, fpf))
+            fg = ctx.force(ctx.half_spinor(), k, n_t, n_max, a.kappa, a.beta, flags=whmc.FORCE_GAUGE)
             rec["F_G2"] = float(torch.dot(fg, fg))
-        r = ctx.hmc_trajectory(p, pi, eta, u)
+            if a.rooted:
+                phi, _ = ctx.rooted_heatbath(eta, p.rooted, a.kappa, solver=p.heatbath_solver)
+                for term in range(1, p.rooted.jmax + 2):
+                    f = ctx.rooted_force(phi, p.rooted, a.kappa, term=term, solver=md)
+                    rec[f"F_PF{term}2"] = float(torch.dot(f, f))
+            else:
+                phi = ctx.heatbath_phi(eta, k, n_t, n_max, a.kappa)
+                fpf = ctx.force(phi, k, n_t, n_max, a.kappa, a.beta, flags=whmc.FORCE_PF, solver=md)
+                rec["F_PF2"] = float(torch.dot(fpf, fpf))
+        r = ctx.rooted_trajectory(p, pi, eta, u) if a.rooted else ctx.hmc_trajectory(p, pi, eta, u)
         rec.update({"plaquette": r["plaquette"], "dH": r["dH"], "accepted": int(r["accepted"]), "u": u,
                     "exp_mdH": math.exp(-r["dH"]) if r["dH"] > -700 else float("inf"),
                     "cg_iters": int(r["cg_iters"]), "n_solves": int(r["n_solves"]), "seconds": r["seconds"]})
+        if a.rooted:
+            rec["poly_iters"] = int(r["poly_iters"])
         log.write(json.dumps(rec) + "\n")
         log.flush()
         done += 1
@@ -158,7 +189,7 @@ def main(argv=None):
     np.save(os.path.join(a.out, "U_last.npy"), ctx.export_gauge().cpu().numpy())
     state = {"next_first": a.first + done, "args": vars(a)}
     if a.compare_solvers:
-        _, eta, _ = draws(torch, dev, a.seed, -1, 0, n_eta)
+        _, eta, _ = draws(torch, dev, a.seed, -1, 0, 24 * Vh)
         state["solvers"] = compare_solvers(ctx, whmc, torch, eta, a.kappa)
         print(f"[ensemble] M_oo x = b on the final field: {state['solvers']}", flush=True)
     json.dump(state, open(os.path.join(a.out, "state.json"), "w"))

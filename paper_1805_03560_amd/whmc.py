@@ -446,6 +446,8 @@ def rooted_hmc_params(beta=5.6, kappa=0.1575, rooted_action=None, integrator=LEA
                       msub=(6, 5, 4), tau=1.4142135623730951, md_solver=None, action_solver=None,
                       heatbath_solver=None):
     """multi-level HMC with the rooted action; msub = (m_0, m_1, ..., m_jmax) as in Sec. 4.2."""
+    if rooted_action is None:
+        raise ValueError("rooted_hmc_params needs rooted_action=whmc.rooted(...)")
     ms = [int(v) for v in msub]
     ms = ms + [1] * (MAX_POLY + 1 - len(ms))
     return RootedHMCParams(beta, kappa, rooted_action, integrator, lam, m, (ctypes.c_int * (MAX_POLY + 1))(*ms), tau,

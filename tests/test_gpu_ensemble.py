@@ -32,3 +32,21 @@ def test_ensemble_run_and_resume(tmp_path):
     for r in ra:
         assert 0.0 < r["plaquette"] < 1.0 and r["F_PF2"] > 0 and r["F_G2"] > 0 and r["cg_iters"] > 0
         assert r["accepted"] == int(r["u"] < min(1.0, r["exp_mdH"]))
+
+
+ROOTED = ["--dims", "4", "4", "4", "4", "--kappa", "0.13", "--filter", "0", "12", "30", "--rooted", "2", "3", "6",
+          "--msub", "2", "1", "2", "--m", "2", "--integrator", "leapfrog", "--tau", "0.5", "--seed", "12", "--forces"]
+
+
+def test_rooted_ensemble_run_and_resume(tmp_path):
+    """the rooted-polynomial mode: one force record per term, and an exact resume."""
+    a, b = str(tmp_path / "a"), str(tmp_path / "b")
+    ensemble.main(ROOTED + ["--ntraj", "2", "--out", a])
+    ensemble.main(ROOTED + ["--ntraj", "1", "--out", b])
+    ensemble.main(ROOTED + ["--ntraj", "1", "--out", b, "--resume", os.path.join(b, "U_last.npy"), "--first", "1"])
+    ra, rb = read(a), read(b)
+    for x, y in zip(ra, rb):
+        for key in ("plaquette", "dH", "accepted", "F_PF12", "F_PF22", "F_PF32", "F_G2", "cg_iters", "poly_iters"):
+            assert x[key] == y[key], key
+    for r in ra:
+        assert r["F_PF12"] > 0 and r["F_PF22"] > 0 and r["F_PF32"] > 0 and r["poly_iters"] > 0
