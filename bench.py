@@ -232,6 +232,7 @@ def extras(ctx, whmc, torch, np, stream, Vh):
 
     out["multi_rhs_24x48"] = multi_rhs(whmc, torch, stream)
     out["hmc_32x64"] = hmc_section(ctx, whmc, torch, stream, Vh)
+    out.update(widened_16x32(whmc, torch))
 
     # kappa^4-filtered pseudo-fermion force (n_t = 15), FP64 solves to 1e-10
     phi = b
@@ -391,6 +392,75 @@ def hmc_section(ctx, whmc, torch, stream, Vh):
                              "rel_err": abs(dd - fd) / abs(fd), "eps": eps, "solver_tol": 1e-14}
     log(f"[bench] force FD check: {out['force_fd_check']}")
     ctx.load_gauge(U0, unitarity_tol=0.0)
+    return out
+
+
+def widened_16x32(whmc, torch):
+    """The rooted-polynomial action (Sec. 2.1) and mass preconditioning with the filter (Sec. 1, 5)
+    on the paper's rooted-polynomial workload, 16^3 x 32 at kappa = 0.1575, here on a synthetic
+    smooth field (width 0.55, seed 3200): heat bath, action and per-term force times, and one
+    multi-level leapfrog / Omelyan trajectory with tau = sqrt(2) (MD solves FP64 to 1e-10, actions
+    to 1e-12).  Rooted: N = 4, n = (8, 32), n_t = 160, n_max = 400, m_0, m_1, m_2 = 6, 5, 4, m = 5
+    (Table RunPoly1).  Mass preconditioning: kappa_1 = 0.14 with the kappa^4 filter (n_t = 15,
+    n_max = 29) on the heavy factor."""
+    import numpy as np
+    from paper_1805_03560_amd import synth
+    dims = (32, 16, 16, 16)
+    kappa = 0.1575
+    U = synth.smooth_links(dims, 3200, width=0.55)
+    ctx = whmc.Context(dims, device=0)
+    ctx.load_gauge(torch.from_numpy(U).to(ctx.device), unitarity_tol=1e-11)
+    U0 = ctx.export_gauge()
+    stream = ctx.stream
+    Vh = ctx.Vh
+    md = whmc.cg_params(tol=1e-10)
+    act = whmc.cg_params(tol=1e-12)
+    pi0 = ctx.pack_algebra(torch.from_numpy(synth.gaussian_momenta(dims, 3201)).to(ctx.device))
+    out = {}
+
+    r = whmc.rooted(4, (8, 32), k=0, n_t=160, n_max=400)
+    nf = r.jmax * r.N + 1
+    eta = ctx.pack_spinor(torch.from_numpy(np.stack([synth.gaussian_spinor(Vh, 3210 + f) for f in range(nf)]))
+                          .to(ctx.device), 0)
+    res = {}
+    t0 = time.perf_counter()
+    phi, it = ctx.rooted_heatbath(eta, r, kappa, solver=act)
+    torch.cuda.synchronize()
+    res["heatbath"] = {"seconds": round(time.perf_counter() - t0, 3), "poly_cg_iters": it}
+    t0 = time.perf_counter()
+    res["action"] = {"S": ctx.rooted_action(phi, r, kappa, solver=act), "seconds": round(time.perf_counter() - t0, 3)}
+    F = ctx.algebra()
+    for term, name in [(1, "force_W1_deg8_x4"), (2, "force_W2_deg32_x4"), (3, "force_remainder_nt160")]:
+        ctx.rooted_force(phi, r, kappa, term=term, solver=md, out=F)
+        res[name + "_ms"] = round(time_events(lambda: ctx.rooted_force(phi, r, kappa, term=term, solver=md, out=F),
+                                              stream, torch), 2)
+    p = whmc.rooted_hmc_params(beta=5.6, kappa=kappa, rooted_action=r, integrator=whmc.LEAPFROG, m=5, msub=(6, 5, 4),
+                               md_solver=md, action_solver=act, heatbath_solver=act)
+    t0 = time.perf_counter()
+    tr = ctx.rooted_trajectory(p, pi0, eta, 0.5)
+    res["trajectory"] = {"seconds": round(time.perf_counter() - t0, 3), "dH": tr["dH"], "cg_iters": tr["cg_iters"],
+                         "n_solves": tr["n_solves"], "poly_iters": tr["poly_iters"]}
+    out["rooted_16x32_kappa0.1575"] = res
+    log(f"[bench] rooted N=4 (8,32) 16^3x32: {res}")
+
+    ctx.load_gauge(U0, unitarity_tol=0.0)
+    mp = whmc.masspre((0.14,), k=2, n_t=15, n_max=29)
+    eta2 = eta[: 2 * 24 * Vh]
+    res = {}
+    phi = ctx.masspre_heatbath(eta2, mp, kappa, solver=act)
+    for term, name in [(1, "force_heavy_kappa0.14_filtered"), (2, "force_ratio")]:
+        ctx.masspre_force(phi, mp, kappa, term=term, solver=md, out=F)
+        res[name + "_ms"] = round(time_events(lambda: ctx.masspre_force(phi, mp, kappa, term=term, solver=md, out=F),
+                                              stream, torch), 2)
+    p = whmc.masspre_hmc_params(beta=5.6, kappa=kappa, mp=mp, integrator=whmc.OMELYAN, m=5, msub=(4, 2),
+                                md_solver=md, action_solver=act)
+    t0 = time.perf_counter()
+    tr = ctx.masspre_trajectory(p, pi0, eta2, 0.5)
+    res["trajectory"] = {"seconds": round(time.perf_counter() - t0, 3), "dH": tr["dH"], "cg_iters": tr["cg_iters"],
+                         "n_solves": tr["n_solves"]}
+    out["masspre_16x32_kappa0.1575"] = res
+    log(f"[bench] mass preconditioning 16^3x32: {res}")
+    ctx.close()
     return out
 
 

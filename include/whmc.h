@@ -349,6 +349,60 @@ whmc_status whmc_rooted_md_integrate(whmc_ctx* ctx, const whmc_rooted_hmc_params
 whmc_status whmc_rooted_hamiltonian(whmc_ctx* ctx, const whmc_rooted_hmc_params* p, const double* pi,
                                     const double* phi, double* H);
 
+/* ------------------------------------------------------------------ mass preconditioning (Sec. 1, 5)
+ * The fermion determinant split into factors with a pseudo-fermion each (Sec. 1), combined with the
+ * kappa^(2k) filter as the conclusion proposes: with heavier hopping parameters
+ * 0 < kappa_1 < ... < kappa_n < kappa_{n+1} = kappa,
+ *   det M_oo(kappa) = det M_oo(kappa_1) prod_{i=1..n} det M_oo(kappa_{i+1}) / det M_oo(kappa_i).
+ * Term 1 is the heaviest factor with the filter at kappa_1 (S = |M~(kappa_1)^{-1} phi_1|^2, gauge
+ * action at beta + 96 kappa_1^4 for k = 2); term i + 1 is the ratio
+ *   S_{i+1} = |M_oo(kappa_{i+1})^{-1} M_oo(kappa_i) phi_{i+1}|^2
+ *           = |(rho_i + (1 - rho_i) M_oo(kappa_{i+1})^{-1}) phi_{i+1}|^2,   rho_i = kappa_i^2 / kappa_{i+1}^2
+ * (the factors commute: both are 1 - kappa^2 H_oe H_eo).  n = 0 is the filter alone at kappa.
+ * phi and eta hold n + 1 odd-site FP64 fields back to back, term 1 first. */
+#define WHMC_MAX_MASSPRE 4
+typedef struct whmc_masspre {
+  int n;                              /* heavier hopping parameters, 0 .. WHMC_MAX_MASSPRE */
+  double kappas[WHMC_MAX_MASSPRE];    /* 0 < kappa_1 < ... < kappa_n < kappa */
+  whmc_filter filter;                 /* filter of the heaviest factor (k <= 2) */
+} whmc_masspre;
+
+/* phi_1 = M~(kappa_1) eta_1 (series at n_max), phi_{i+1} = M_oo(kappa_i)^{-1} M_oo(kappa_{i+1}) eta_{i+1}
+ * (one solve at kappa_i each).  solver may be NULL (FP64 CG to 1e-12). */
+whmc_status whmc_masspre_heatbath(whmc_ctx* ctx, double* phi, const double* eta, const whmc_masspre* mp,
+                                  double kappa, const whmc_cg_params* solver);
+
+/* S[0 .. n]: the heavy filtered term, then the ratios. */
+whmc_status whmc_masspre_action(whmc_ctx* ctx, double* S, const double* phi, const whmc_masspre* mp, double kappa,
+                                const whmc_cg_params* solver);
+
+/* Force of term 1 .. n + 1 (0: all), algebra layout; flags: WHMC_FORCE_ACCUMULATE. */
+whmc_status whmc_masspre_force(whmc_ctx* ctx, double* F, const double* phi, const whmc_masspre* mp, int term,
+                               double kappa, const whmc_cg_params* solver, int flags);
+
+/* Multi-level trajectory: gauge action on level 0, term t on level t (the heavy filtered field on
+ * level 1, the lightest ratio outermost with m steps); msub[l-1] steps of level l - 1 per (half)
+ * step of level l.  Otherwise as whmc_hmc_trajectory; eta holds the n + 1 Gaussian sources. */
+typedef struct whmc_masspre_hmc_params {
+  double beta;
+  double kappa;
+  whmc_masspre mp;
+  int integrator;
+  double lambda;
+  int m;
+  int msub[WHMC_MAX_MASSPRE + 1];
+  double tau;
+  whmc_cg_params md_solver;
+  whmc_cg_params action_solver;
+} whmc_masspre_hmc_params;
+
+whmc_status whmc_masspre_trajectory(whmc_ctx* ctx, const whmc_masspre_hmc_params* p, const double* pi0,
+                                    const double* eta, double u, whmc_traj_result* res);
+whmc_status whmc_masspre_md_integrate(whmc_ctx* ctx, const whmc_masspre_hmc_params* p, double* pi,
+                                      const double* phi);
+whmc_status whmc_masspre_hamiltonian(whmc_ctx* ctx, const whmc_masspre_hmc_params* p, const double* pi,
+                                     const double* phi, double* H);
+
 #ifdef __cplusplus
 }
 #endif

@@ -70,7 +70,7 @@ whmc_cg_params default_solver() {
   return p;
 }
 
-static whmc_status check_filter(const whmc_filter* f) {
+whmc_status check_filter(const whmc_filter* f) {
   WHMC_CHECK(f, WHMC_EARG, "null filter");
   WHMC_CHECK(f->k >= 0 && f->n_t >= 0 && f->n_max >= 0, WHMC_EARG, "filter: k, n_t, n_max must be >= 0");
   WHMC_CHECK(f->k <= 2, WHMC_EUNSUP, "filter: only k <= 2 has a closed-form gauge term (Sec. 2)");
@@ -330,6 +330,69 @@ whmc_status md_levels(whmc_ctx* c, double* pi, const std::vector<MDLevel>& lv, i
   const int top = (int)lv.size() - 1;
   for (int k = 0; k < m; ++k) WHMC_TRY(r.run(top, tau / m));
   return r.flush();
+}
+
+whmc_status term_hamiltonian(whmc_ctx* c, const TermAction& A, const double* pi, const double* phi, double* H,
+                             SolveLog* log) {
+  double pp, plaq;
+  std::vector<double> S(A.nterms);
+  WHMC_TRY(algebra_norm2(c, pi, &pp));
+  WHMC_TRY(plaquette_sum(c, &plaq));
+  WHMC_TRY(A.action(S.data(), phi, log));
+  *H = 0.5 * pp - A.beta_eff / 3.0 * plaq;
+  for (double v : S) *H += v;
+  return WHMC_OK;
+}
+
+whmc_status term_md(whmc_ctx* c, const TermAction& A, const TermMD& md, double* pi, const double* phi,
+                    SolveLog* log) {
+  std::vector<MDLevel> lv(A.nterms + 1);
+  const double beff = A.beta_eff;
+  lv[0].force = [=](double s) { return gauge_force(c, pi, beff, s, 1); };
+  for (int t = 1; t <= A.nterms; ++t) {
+    lv[t].force = [=, &A](double s) { return A.force(pi, phi, t, s, 1, log); };
+    lv[t].nsub = md.msub[t - 1];
+  }
+  return md_levels(c, pi, lv, md.integrator, md.lambda, md.tau, md.m);
+}
+
+// heat bath, H0, molecular dynamics, H1, Metropolis; the gauge field is restored on rejection
+whmc_status term_trajectory(whmc_ctx* c, const TermAction& A, const TermMD& md, const double* pi0, const double* eta,
+                            double u, whmc_traj_result* res) {
+  const auto t0 = std::chrono::steady_clock::now();
+  void *pi, *phi, *Usave;
+  const size_t ab = (size_t)64 * c->Vh * sizeof(double);
+  const size_t ub = (size_t)8 * 9 * c->Vh * sizeof(double2);
+  WHMC_TRY(workspace(c, "term_pi", ab, &pi));
+  WHMC_TRY(workspace(c, "term_phi", (size_t)A.nfields * c->Vh * 192, &phi));
+  WHMC_TRY(workspace(c, "hmc_Usave", ub, &Usave));
+  WHMC_HIP(hipMemcpyAsync(pi, pi0, ab, hipMemcpyDeviceToDevice, c->stream));
+  WHMC_HIP(hipMemcpyAsync(Usave, c->U18, ub, hipMemcpyDeviceToDevice, c->stream));
+  long long hb_iters = 0;
+  WHMC_TRY(A.heatbath((double*)phi, eta, &hb_iters));
+  SolveLog log, mdlog;
+  double H0, H1;
+  WHMC_TRY(term_hamiltonian(c, A, (double*)pi, (double*)phi, &H0, &log));
+  WHMC_TRY(term_md(c, A, md, (double*)pi, (const double*)phi, &mdlog));
+  WHMC_TRY(term_hamiltonian(c, A, (double*)pi, (double*)phi, &H1, &log));
+  const double dH = H1 - H0;
+  const bool acc = u < std::exp(-dH);
+  if (!acc) {
+    WHMC_HIP(hipMemcpyAsync(c->U18, Usave, ub, hipMemcpyDeviceToDevice, c->stream));
+    WHMC_TRY(gauge_changed(c));
+  }
+  double plaq;
+  WHMC_TRY(plaquette_sum(c, &plaq));
+  res->dH = dH;
+  res->H0 = H0;
+  res->H1 = H1;
+  res->accepted = acc ? 1 : 0;
+  res->plaquette = plaq / (18.0 * (double)c->V);
+  res->cg_iters = log.iters + mdlog.iters;
+  res->n_solves = log.n + mdlog.n;
+  res->poly_iters = hb_iters;
+  res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return WHMC_OK;
 }
 
 // gauge action on level 0, the filtered pseudo-fermion action on level 1

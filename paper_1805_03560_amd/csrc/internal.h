@@ -175,7 +175,35 @@ whmc_status series_inverse(whmc_ctx* c, double* out, const double* phi, std::vec
 whmc_status series_force(whmc_ctx* c, double* out, const double* phi, const std::vector<double>& b, double alpha,
                          double kappa, const whmc_cg_params* sp, double scale, int accumulate, SolveLog* log);
 whmc_status heatbath(whmc_ctx* c, double* phi, const double* eta, const whmc_filter* f, double kappa);
+whmc_status check_filter(const whmc_filter* f);
+whmc_status pf_action(whmc_ctx* c, const double* phi, const whmc_filter* f, double kappa, const whmc_cg_params* sp,
+                      double* S, SolveLog* log);
+whmc_status pf_force(whmc_ctx* c, double* out, const double* phi, const whmc_filter* f, double kappa,
+                     const whmc_cg_params* sp, double scale, int accumulate, SolveLog* log);
 whmc_status md_levels(whmc_ctx* c, double* pi, const std::vector<MDLevel>& lv, int integrator, double lambda,
                       double tau, int m);
+
+// A pseudo-fermion action of several terms (term t on MD level t, the gauge action on level 0),
+// with the trajectory that the rooted and the mass-preconditioned actions share.
+struct TermAction {
+  int nfields = 1;          // odd-site FP64 fields in phi and eta
+  int nterms = 1;           // pseudo-fermion terms
+  double beta_eff = 0.0;    // gauge coupling including the filter's shift
+  std::function<whmc_status(double* phi, const double* eta, long long* iters)> heatbath;
+  std::function<whmc_status(double* S, const double* phi, SolveLog* log)> action;   // S[0 .. nterms)
+  // F (or pi) += scale * force of term t (1 .. nterms); overwrite unless accumulate
+  std::function<whmc_status(double* F, const double* phi, int t, double scale, int accumulate, SolveLog* log)> force;
+};
+struct TermMD {
+  int integrator;
+  double lambda, tau;
+  int m;            // steps of the outermost term per trajectory
+  const int* msub;  // msub[l-1]: level l-1 steps per step of level l
+};
+whmc_status term_hamiltonian(whmc_ctx* c, const TermAction& A, const double* pi, const double* phi, double* H,
+                             SolveLog* log);
+whmc_status term_md(whmc_ctx* c, const TermAction& A, const TermMD& md, double* pi, const double* phi, SolveLog* log);
+whmc_status term_trajectory(whmc_ctx* c, const TermAction& A, const TermMD& md, const double* pi0, const double* eta,
+                            double u, whmc_traj_result* res);
 
 }  // namespace whmc

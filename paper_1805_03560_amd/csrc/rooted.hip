@@ -16,7 +16,6 @@
 // polynomial terms: no solve).  The integrator nests the gauge action, the jmax polynomial terms
 // and the remainder on jmax + 2 Sexton-Weingarten levels.
 #include <algorithm>
-#include <chrono>
 #include <cmath>
 #include <vector>
 
@@ -227,31 +226,25 @@ whmc_status force_term(whmc_ctx* c, double* F, const double* phi, const whmc_roo
   return series_force(c, F, field(c, phi, r.jmax * r.N), b, C.alpha, kappa, sp, scale, accumulate, log);
 }
 
-whmc_status hamiltonian(whmc_ctx* c, const whmc_rooted_hmc_params* p, const RootedCoef& C, const double* pi,
-                        const double* phi, double* H, SolveLog* log) {
-  double pp, plaq;
-  std::vector<double> S(p->rooted.jmax + 1);
-  WHMC_TRY(algebra_norm2(c, pi, &pp));
-  WHMC_TRY(plaquette_sum(c, &plaq));
-  WHMC_TRY(action_all(c, S.data(), phi, p->rooted, C, p->kappa, &p->action_solver, log));
-  const double beff = p->beta + delta_beta(p->kappa, p->rooted.k);
-  *H = 0.5 * pp - beff / 3.0 * plaq;
-  for (double s : S) *H += s;
-  return WHMC_OK;
+// the terms of the rooted action for the shared multi-level trajectory (C must outlive the result)
+TermAction rooted_terms(whmc_ctx* c, const whmc_rooted_hmc_params* p, const RootedCoef& C) {
+  TermAction A;
+  A.nfields = n_fields(p->rooted);
+  A.nterms = p->rooted.jmax + 1;
+  A.beta_eff = p->beta + delta_beta(p->kappa, p->rooted.k);
+  A.heatbath = [=, &C](double* phi, const double* eta, long long* it) {
+    return heatbath_all(c, phi, eta, p->rooted, C, p->kappa, &p->heatbath_solver, it);
+  };
+  A.action = [=, &C](double* S, const double* phi, SolveLog* log) {
+    return action_all(c, S, phi, p->rooted, C, p->kappa, &p->action_solver, log);
+  };
+  A.force = [=, &C](double* F, const double* phi, int t, double s, int acc, SolveLog* log) {
+    return force_term(c, F, phi, p->rooted, C, t, p->kappa, &p->md_solver, s, acc, log);
+  };
+  return A;
 }
 
-whmc_status md(whmc_ctx* c, const whmc_rooted_hmc_params* p, const RootedCoef& C, double* pi, const double* phi,
-               SolveLog* log) {
-  const whmc_rooted& r = p->rooted;
-  const double beff = p->beta + delta_beta(p->kappa, r.k);
-  std::vector<MDLevel> lv(r.jmax + 2);
-  lv[0].force = [=](double s) { return gauge_force(c, pi, beff, s, 1); };
-  for (int l = 1; l <= r.jmax + 1; ++l) {
-    lv[l].force = [=, &C](double s) { return force_term(c, pi, phi, r, C, l, p->kappa, &p->md_solver, s, 1, log); };
-    lv[l].nsub = p->msub[l - 1];
-  }
-  return md_levels(c, pi, lv, p->integrator, p->lambda, p->tau, p->m);
-}
+TermMD rooted_md(const whmc_rooted_hmc_params* p) { return TermMD{p->integrator, p->lambda, p->tau, p->m, p->msub}; }
 
 }  // namespace
 }  // namespace whmc
@@ -322,7 +315,7 @@ whmc_status whmc_rooted_hamiltonian(whmc_ctx* c, const whmc_rooted_hmc_params* p
   WHMC_CHECK(c->gauge_loaded, WHMC_ESTATE, "no gauge field loaded");
   RootedCoef C;
   rooted_coefficients(p->rooted, p->rooted.n_max, C);
-  return hamiltonian(c, p, C, pi, phi, H, nullptr);
+  return term_hamiltonian(c, rooted_terms(c, p, C), pi, phi, H, nullptr);
 }
 
 whmc_status whmc_rooted_md_integrate(whmc_ctx* c, const whmc_rooted_hmc_params* p, double* pi, const double* phi) {
@@ -331,7 +324,7 @@ whmc_status whmc_rooted_md_integrate(whmc_ctx* c, const whmc_rooted_hmc_params* 
   WHMC_CHECK(c->gauge_loaded, WHMC_ESTATE, "no gauge field loaded");
   RootedCoef C;
   rooted_coefficients(p->rooted, p->rooted.n_t, C);
-  WHMC_TRY(md(c, p, C, pi, phi, nullptr));
+  WHMC_TRY(term_md(c, rooted_terms(c, p, C), rooted_md(p), pi, phi, nullptr));
   WHMC_HIP(hipStreamSynchronize(c->stream));
   return WHMC_OK;
 }
@@ -341,43 +334,9 @@ whmc_status whmc_rooted_trajectory(whmc_ctx* c, const whmc_rooted_hmc_params* p,
   WHMC_CHECK(c && pi0 && eta && res, WHMC_EARG, "whmc_rooted_trajectory: null argument");
   WHMC_TRY(check_rooted_hmc(p));
   WHMC_CHECK(c->gauge_loaded, WHMC_ESTATE, "no gauge field loaded");
-  const auto t0 = std::chrono::steady_clock::now();
-  const whmc_rooted& r = p->rooted;
   RootedCoef C;
-  rooted_coefficients(r, std::max(r.n_t, r.n_max), C);
-  void *pi, *phi, *Usave;
-  const size_t ab = (size_t)64 * c->Vh * sizeof(double);
-  const size_t ub = (size_t)8 * 9 * c->Vh * sizeof(double2);
-  WHMC_TRY(workspace(c, "rhmc_pi", ab, &pi));
-  WHMC_TRY(workspace(c, "rhmc_phi", (size_t)n_fields(r) * c->Vh * 192, &phi));
-  WHMC_TRY(workspace(c, "hmc_Usave", ub, &Usave));
-  WHMC_HIP(hipMemcpyAsync(pi, pi0, ab, hipMemcpyDeviceToDevice, c->stream));
-  WHMC_HIP(hipMemcpyAsync(Usave, c->U18, ub, hipMemcpyDeviceToDevice, c->stream));
-  long long piters = 0;
-  WHMC_TRY(heatbath_all(c, (double*)phi, eta, r, C, p->kappa, &p->heatbath_solver, &piters));
-  SolveLog log, mdlog;
-  double H0, H1;
-  WHMC_TRY(hamiltonian(c, p, C, (double*)pi, (double*)phi, &H0, &log));
-  WHMC_TRY(md(c, p, C, (double*)pi, (const double*)phi, &mdlog));
-  WHMC_TRY(hamiltonian(c, p, C, (double*)pi, (double*)phi, &H1, &log));
-  const double dH = H1 - H0;
-  const bool acc = u < std::exp(-dH);
-  if (!acc) {
-    WHMC_HIP(hipMemcpyAsync(c->U18, Usave, ub, hipMemcpyDeviceToDevice, c->stream));
-    WHMC_TRY(gauge_changed(c));
-  }
-  double plaq;
-  WHMC_TRY(plaquette_sum(c, &plaq));
-  res->dH = dH;
-  res->H0 = H0;
-  res->H1 = H1;
-  res->accepted = acc ? 1 : 0;
-  res->plaquette = plaq / (18.0 * (double)c->V);
-  res->cg_iters = log.iters + mdlog.iters;
-  res->n_solves = log.n + mdlog.n;
-  res->poly_iters = piters;
-  res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  return WHMC_OK;
+  rooted_coefficients(p->rooted, std::max(p->rooted.n_t, p->rooted.n_max), C);
+  return term_trajectory(c, rooted_terms(c, p, C), rooted_md(p), pi0, eta, u, res);
 }
 
 }  // extern "C"

@@ -25,6 +25,10 @@ multi-level scheme of Sec. 4.2: --msub m_0 .. m_jmax, --m remainder steps, e.g. 
     python -m paper_1805_03560_amd.ensemble --dims 32 16 16 16 --beta 5.6 --kappa 0.1575 \\
         --filter 0 160 400 --rooted 4 8 32 --msub 6 5 4 --m 5 --integrator leapfrog --out run_N4
 
+With --masspre kappa_1 .. kappa_n the determinant is split by mass preconditioning (Sec. 1, 5):
+the heaviest factor carries the filter of --filter at kappa_1, each ratio
+det M_oo(kappa_{i+1}) / det M_oo(kappa_i) has its own field and level (--msub m_0 .. m_n).
+
 Writes <out>/traj.jsonl (one JSON record per trajectory) and <out>/U_last.npy (the gauge field
 after the last trajectory, complex128 (L_t, L_z, L_y, L_x, 4, 3, 3)).
 """
@@ -62,8 +66,10 @@ def parse(argv=None):
                          "bitwise reproducible: the blocking sets the summation order of the reductions)")
     ap.add_argument("--rooted", type=int, nargs="+", default=None, metavar="N_OR_DEGREE",
                     help="rooted polynomials: root order N, then the degrees n_1 .. n_jmax (Sec. 2.1)")
+    ap.add_argument("--masspre", type=float, nargs="+", default=None, metavar="KAPPA_I",
+                    help="mass preconditioning: heavier hopping parameters kappa_1 < ... < kappa_n (Sec. 1, 5)")
     ap.add_argument("--msub", type=int, nargs="+", default=None,
-                    help="rooted action: m_0 .. m_jmax, steps of level l-1 per step of level l")
+                    help="rooted / mass-preconditioned action: steps of level l-1 per step of level l, l = 1 ..")
     ap.add_argument("--heatbath-tol", type=float, default=1e-12, help="rooted action: CG on p_j^dag p_j")
     ap.add_argument("--forces", action="store_true", help="record (F,F) of every force at each start")
     ap.add_argument("--max-seconds", type=float, default=None, help="stop after this much wall time")
@@ -138,7 +144,17 @@ def main(argv=None):
     integ = whmc.OMELYAN if a.integrator == "omelyan" else whmc.LEAPFROG
     md = whmc.cg_params(tol=a.md_tol, rhs_block=1, rhs_lanes=a.rhs_lanes)
     act = whmc.cg_params(tol=a.action_tol)
-    if a.rooted:
+    if a.rooted and a.masspre:
+        raise SystemExit("--rooted and --masspre are separate actions")
+    if a.masspre:
+        mp = whmc.masspre(a.masspre, k=k, n_t=n_t, n_max=n_max)
+        msub = a.msub or [a.m0] + [1] * mp.n
+        if len(msub) != mp.n + 1:
+            raise SystemExit("--msub needs m_0 .. m_n (one more value than there are heavier kappas)")
+        p = whmc.masspre_hmc_params(beta=a.beta, kappa=a.kappa, mp=mp, integrator=integ, lam=a.lam, m=a.m,
+                                    msub=msub, tau=a.tau, md_solver=md, action_solver=act)
+        n_fields = mp.n + 1
+    elif a.rooted:
         r = whmc.rooted(a.rooted[0], a.rooted[1:], k=k, n_t=n_t, n_max=n_max)
         msub = a.msub or [a.m0] + [1] * r.jmax
         if len(msub) != r.jmax + 1:
@@ -160,9 +176,15 @@ def main(argv=None):
         pi, eta, u = draws(torch, dev, a.seed, traj, n_pi, n_eta)
         rec = {"traj": traj}
         if a.forces:
-            fg = ctx.force(ctx.half_spinor(), k, n_t, n_max, a.kappa, a.beta, flags=whmc.FORCE_GAUGE)
+            k_heavy = a.masspre[0] if a.masspre else a.kappa   # the filter's gauge shift sits at kappa_1
+            fg = ctx.force(ctx.half_spinor(), k, n_t, n_max, k_heavy, a.beta, flags=whmc.FORCE_GAUGE)
             rec["F_G2"] = float(torch.dot(fg, fg))
-            if a.rooted:
+            if a.masspre:
+                phi = ctx.masspre_heatbath(eta, p.mp, a.kappa, solver=act)
+                for term in range(1, p.mp.n + 2):
+                    f = ctx.masspre_force(phi, p.mp, a.kappa, term=term, solver=md)
+                    rec[f"F_PF{term}2"] = float(torch.dot(f, f))
+            elif a.rooted:
                 phi, _ = ctx.rooted_heatbath(eta, p.rooted, a.kappa, solver=p.heatbath_solver)
                 for term in range(1, p.rooted.jmax + 2):
                     f = ctx.rooted_force(phi, p.rooted, a.kappa, term=term, solver=md)
@@ -171,7 +193,12 @@ def main(argv=None):
                 phi = ctx.heatbath_phi(eta, k, n_t, n_max, a.kappa)
                 fpf = ctx.force(phi, k, n_t, n_max, a.kappa, a.beta, flags=whmc.FORCE_PF, solver=md)
                 rec["F_PF2"] = float(torch.dot(fpf, fpf))
-        r = ctx.rooted_trajectory(p, pi, eta, u) if a.rooted else ctx.hmc_trajectory(p, pi, eta, u)
+        if a.masspre:
+            r = ctx.masspre_trajectory(p, pi, eta, u)
+        elif a.rooted:
+            r = ctx.rooted_trajectory(p, pi, eta, u)
+        else:
+            r = ctx.hmc_trajectory(p, pi, eta, u)
         rec.update({"plaquette": r["plaquette"], "dH": r["dH"], "accepted": int(r["accepted"]), "u": u,
                     "exp_mdH": math.exp(-r["dH"]) if r["dH"] > -700 else float("inf"),
                     "cg_iters": int(r["cg_iters"]), "n_solves": int(r["n_solves"]), "seconds": r["seconds"]})

@@ -78,6 +78,30 @@ class RootedHMCParams(ctypes.Structure):
                 ("action_solver", CGParams), ("heatbath_solver", CGParams)]
 
 
+MAX_MASSPRE = 4
+
+
+class MassPre(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("kappas", ctypes.c_double * MAX_MASSPRE), ("filter", Filter)]
+
+
+class MassPreHMCParams(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("kappa", ctypes.c_double), ("mp", MassPre),
+                ("integrator", ctypes.c_int), ("lam", ctypes.c_double), ("m", ctypes.c_int),
+                ("msub", ctypes.c_int * (MAX_MASSPRE + 1)), ("tau", ctypes.c_double), ("md_solver", CGParams),
+                ("action_solver", CGParams)]
+
+
+def masspre(kappas, k=2, n_t=15, n_max=29):
+    """mass preconditioning with heavier hopping parameters kappas (increasing), the kappa^(2k)
+    filter on the heaviest factor (Sec. 1, 5)."""
+    ks = [float(v) for v in kappas]
+    if len(ks) > MAX_MASSPRE:
+        raise ValueError(f"at most {MAX_MASSPRE} heavier kappas")
+    return MassPre(len(ks), (ctypes.c_double * MAX_MASSPRE)(*(ks + [0.0] * (MAX_MASSPRE - len(ks)))),
+                   Filter(k, n_t, n_max))
+
+
 def rooted(N, ns, k=0, n_t=0, n_max=0):
     """rooted-polynomial action (Sec. 2.1): root order N, degrees ns = (n_1, ..., n_jmax)."""
     ns = [int(v) for v in ns]
@@ -148,6 +172,17 @@ _SIGS = {
     "whmc_rooted_md_integrate": ([_P, ctypes.POINTER(RootedHMCParams), _P, _P], ctypes.c_int),
     "whmc_rooted_hamiltonian": ([_P, ctypes.POINTER(RootedHMCParams), _P, _P, ctypes.POINTER(ctypes.c_double)],
                                 ctypes.c_int),
+    "whmc_masspre_heatbath": ([_P, _P, _P, ctypes.POINTER(MassPre), ctypes.c_double, ctypes.POINTER(CGParams)],
+                              ctypes.c_int),
+    "whmc_masspre_action": ([_P, ctypes.POINTER(ctypes.c_double), _P, ctypes.POINTER(MassPre), ctypes.c_double,
+                             ctypes.POINTER(CGParams)], ctypes.c_int),
+    "whmc_masspre_force": ([_P, _P, _P, ctypes.POINTER(MassPre), ctypes.c_int, ctypes.c_double,
+                            ctypes.POINTER(CGParams), ctypes.c_int], ctypes.c_int),
+    "whmc_masspre_trajectory": ([_P, ctypes.POINTER(MassPreHMCParams), _P, _P, ctypes.c_double,
+                                 ctypes.POINTER(TrajResult)], ctypes.c_int),
+    "whmc_masspre_md_integrate": ([_P, ctypes.POINTER(MassPreHMCParams), _P, _P], ctypes.c_int),
+    "whmc_masspre_hamiltonian": ([_P, ctypes.POINTER(MassPreHMCParams), _P, _P, ctypes.POINTER(ctypes.c_double)],
+                                 ctypes.c_int),
 }
 
 
@@ -403,6 +438,41 @@ class Context:
         _check(lib().whmc_hamiltonian(self._h, ctypes.byref(params), _ptr(pi), _ptr(phi), ctypes.byref(h)))
         return h.value
 
+    # ------------------------------------------------------------ mass preconditioning (Sec. 1, 5)
+    def masspre_heatbath(self, eta, mp, kappa, solver=None):
+        phi = torch.empty_like(eta)
+        _check(lib().whmc_masspre_heatbath(self._h, _ptr(phi), _ptr(eta), ctypes.byref(mp), float(kappa),
+                                           ctypes.byref(solver) if solver is not None else None))
+        return phi
+
+    def masspre_action(self, phi, mp, kappa, solver=None):
+        S = (ctypes.c_double * (mp.n + 1))()
+        _check(lib().whmc_masspre_action(self._h, S, _ptr(phi), ctypes.byref(mp), float(kappa),
+                                         ctypes.byref(solver) if solver is not None else None))
+        return list(S)
+
+    def masspre_force(self, phi, mp, kappa, term=0, solver=None, out=None, accumulate=False):
+        out = self.algebra() if out is None else out
+        _check(lib().whmc_masspre_force(self._h, _ptr(out), _ptr(phi), ctypes.byref(mp), int(term), float(kappa),
+                                        ctypes.byref(solver) if solver is not None else None,
+                                        FORCE_ACCUMULATE if accumulate else 0))
+        return out
+
+    def masspre_trajectory(self, params, pi0, eta, u):
+        res = TrajResult()
+        _check(lib().whmc_masspre_trajectory(self._h, ctypes.byref(params), _ptr(pi0), _ptr(eta), float(u),
+                                             ctypes.byref(res)))
+        return res.as_dict()
+
+    def masspre_md_integrate(self, params, pi, phi):
+        _check(lib().whmc_masspre_md_integrate(self._h, ctypes.byref(params), _ptr(pi), _ptr(phi)))
+        return pi
+
+    def masspre_hamiltonian(self, params, pi, phi):
+        h = ctypes.c_double()
+        _check(lib().whmc_masspre_hamiltonian(self._h, ctypes.byref(params), _ptr(pi), _ptr(phi), ctypes.byref(h)))
+        return h.value
+
     # ------------------------------------------------------------ rooted polynomials (Sec. 2.1)
     def rooted_heatbath(self, eta, r, kappa, solver=None):
         """(phi, iterations): the jmax*N + 1 fields of the rooted action from the sources eta."""
@@ -453,6 +523,17 @@ def rooted_hmc_params(beta=5.6, kappa=0.1575, rooted_action=None, integrator=LEA
     return RootedHMCParams(beta, kappa, rooted_action, integrator, lam, m, (ctypes.c_int * (MAX_POLY + 1))(*ms), tau,
                            md_solver or cg_params(tol=1e-12), action_solver or cg_params(tol=1e-12),
                            heatbath_solver or cg_params(tol=1e-12))
+
+
+def masspre_hmc_params(beta=5.6, kappa=0.156, mp=None, integrator=OMELYAN, lam=1.0 / 6.0, m=6, msub=(4, 1),
+                       tau=1.4142135623730951, md_solver=None, action_solver=None):
+    """multi-level HMC with mass preconditioning; msub = (m_0, m_1, ..., m_n)."""
+    if mp is None:
+        raise ValueError("masspre_hmc_params needs mp=whmc.masspre(...)")
+    ms = [int(v) for v in msub]
+    ms = ms + [1] * (MAX_MASSPRE + 1 - len(ms))
+    return MassPreHMCParams(beta, kappa, mp, integrator, lam, m, (ctypes.c_int * (MAX_MASSPRE + 1))(*ms), tau,
+                            md_solver or cg_params(tol=1e-12), action_solver or cg_params(tol=1e-12))
 
 
 def hmc_params(beta=5.6, kappa=0.156, k=0, n_t=0, n_max=0, integrator=OMELYAN, lam=1.0 / 6.0, m=10, m0=4, tau=1.0,

@@ -50,3 +50,20 @@ def test_rooted_ensemble_run_and_resume(tmp_path):
             assert x[key] == y[key], key
     for r in ra:
         assert r["F_PF12"] > 0 and r["F_PF22"] > 0 and r["F_PF32"] > 0 and r["poly_iters"] > 0
+
+
+MASSPRE = ["--dims", "4", "4", "4", "4", "--kappa", "0.15", "--filter", "2", "7", "29", "--masspre", "0.12",
+           "--msub", "2", "2", "--m", "2", "--integrator", "omelyan", "--tau", "0.5", "--seed", "13", "--forces"]
+
+
+def test_masspre_ensemble_run_and_resume(tmp_path):
+    a, b = str(tmp_path / "a"), str(tmp_path / "b")
+    ensemble.main(MASSPRE + ["--ntraj", "2", "--out", a])
+    ensemble.main(MASSPRE + ["--ntraj", "1", "--out", b])
+    ensemble.main(MASSPRE + ["--ntraj", "1", "--out", b, "--resume", os.path.join(b, "U_last.npy"), "--first", "1"])
+    ra, rb = read(a), read(b)
+    for x, y in zip(ra, rb):
+        for key in ("plaquette", "dH", "accepted", "F_PF12", "F_PF22", "F_G2", "cg_iters"):
+            assert x[key] == y[key], key
+    for r in ra:
+        assert r["F_PF12"] > 0 and r["F_PF22"] > 0 and r["cg_iters"] > 0
