@@ -89,6 +89,14 @@ def summarize(records, therm=0):
             v = np.asarray(v)
             m4, e4, _ = mean_err((v - v.mean()) ** 2)
             out[f"var_{key}"] = {"value": float(np.var(v)), "err": e4, "mean": float(v.mean())}
+    # Delta H probes at other force truncations from the same starting points (ensemble --probe-nt)
+    for key in sorted({k for r in recs for k in r if k.startswith("dH_nt")}, key=lambda k: int(k[5:])):
+        v = np.array([r[key] for r in recs if key in r])
+        if len(v) > 2:
+            m, e, _ = mean_err(np.minimum(1.0, np.exp(-np.clip(v, -700, 700))))
+            m2, e2, _ = mean_err((v - v.mean()) ** 2)
+            out[f"probe_n_t={key[5:]}"] = {"P_acc": m, "P_acc_err": e, "var_dH": float(np.var(v)), "var_dH_err": e2,
+                                           "n": int(len(v))}
     return out
 
 

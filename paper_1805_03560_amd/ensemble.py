@@ -72,6 +72,10 @@ def parse(argv=None):
                     help="rooted / mass-preconditioned action: steps of level l-1 per step of level l, l = 1 ..")
     ap.add_argument("--heatbath-tol", type=float, default=1e-12, help="rooted action: CG on p_j^dag p_j")
     ap.add_argument("--forces", action="store_true", help="record (F,F) of every force at each start")
+    ap.add_argument("--probe-nt", type=int, nargs="+", default=None, metavar="N_T",
+                    help="filter action only: at each trajectory start also integrate the same (U, pi, phi) with "
+                         "these force truncations and record their Delta H (field not updated); the equilibrium "
+                         "does not depend on n_t, so averages over the run give P_acc(n_t) (Sec. 4.1)")
     ap.add_argument("--max-seconds", type=float, default=None, help="stop after this much wall time")
     ap.add_argument("--compare-solvers", action="store_true",
                     help="at the end, time BiCGstab on M_oo against CG on the normal equations on the final field")
@@ -110,6 +114,23 @@ def compare_solvers(ctx, whmc, torch, b, kappa):
                                   "residual_Moo": r, "cg_tol": tol}
     res["speedup_bicgstab_vs_cgne"] = round(res["cg_normal_equations"]["ms"] / res["bicgstab"]["ms"], 3)
     return res
+
+
+def probe_nt(ctx, whmc, a, p, pi, eta, rec):
+    """Delta H of the molecular dynamics from the current field with each n_t in a.probe_nt
+    (same pi and phi as the trajectory that follows); the field is restored afterwards."""
+    k, _, n_max = a.filter
+    U0 = ctx.export_gauge()
+    phi = ctx.heatbath_phi(eta, k, p.filter.n_t, n_max, a.kappa)
+    H0 = ctx.hamiltonian(p, pi, phi)
+    for nt in a.probe_nt:
+        q = whmc.hmc_params(beta=a.beta, kappa=a.kappa, k=k, n_t=nt, n_max=n_max, integrator=p.integrator,
+                            lam=p.lam, m=p.m, m0=p.m0, tau=p.tau, md_solver=p.md_solver,
+                            action_solver=p.action_solver)
+        pic = pi.clone()
+        ctx.md_integrate(q, pic, phi)
+        rec[f"dH_nt{nt}"] = ctx.hamiltonian(q, pic, phi) - H0
+        ctx.load_gauge(U0, unitarity_tol=0.0)
 
 
 def draws(torch, dev, seed, traj, n_pi, n_eta):
@@ -193,6 +214,10 @@ def main(argv=None):
                 phi = ctx.heatbath_phi(eta, k, n_t, n_max, a.kappa)
                 fpf = ctx.force(phi, k, n_t, n_max, a.kappa, a.beta, flags=whmc.FORCE_PF, solver=md)
                 rec["F_PF2"] = float(torch.dot(fpf, fpf))
+        if a.probe_nt:
+            if a.rooted or a.masspre:
+                raise SystemExit("--probe-nt applies to the filter action only")
+            probe_nt(ctx, whmc, a, p, pi, eta, rec)
         if a.masspre:
             r = ctx.masspre_trajectory(p, pi, eta, u)
         elif a.rooted:

@@ -65,3 +65,12 @@ def test_summarize_synthetic_run():
     assert s["P_acc"]["mean"] == pytest.approx(s["P_acc_from_var_dH"], abs=0.02)
     assert s["exp_minus_dH"]["mean"] == pytest.approx(1.0, abs=0.05)
     assert s["var_F_PF2"]["value"] == pytest.approx(1.0, rel=0.15)
+
+
+def test_probe_columns_are_summarised():
+    recs = [{"traj": i, "plaquette": 0.5, "dH": 0.1 * (-1) ** i, "accepted": 1, "cg_iters": 1, "seconds": 0.1,
+             "dH_nt5": 0.2 * (-1) ** i, "dH_nt15": 0.1 * (-1) ** i} for i in range(40)]
+    s = analysis.summarize(recs)
+    assert s["probe_n_t=5"]["var_dH"] == pytest.approx(0.04)
+    assert s["probe_n_t=15"]["P_acc"] == pytest.approx(0.5 * (1 + np.exp(-0.1)))
+    assert list(k for k in s if k.startswith("probe")) == ["probe_n_t=5", "probe_n_t=15"]

@@ -67,3 +67,16 @@ def test_masspre_ensemble_run_and_resume(tmp_path):
             assert x[key] == y[key], key
     for r in ra:
         assert r["F_PF12"] > 0 and r["F_PF22"] > 0 and r["cg_iters"] > 0
+
+
+def test_probe_nt_reproduces_the_trajectory_at_its_own_n_t(tmp_path):
+    """a probe at the production n_t integrates the same (U, pi, phi): its Delta H is the
+    trajectory's; other n_t give other Delta H, and the field is left as the trajectory found it."""
+    a = str(tmp_path / "a")
+    ensemble.main(ARGS + ["--ntraj", "2", "--out", a, "--probe-nt", "6", "3"])
+    b = str(tmp_path / "b")
+    ensemble.main(ARGS + ["--ntraj", "2", "--out", b])
+    for x, y in zip(read(a), read(b)):
+        assert x["dH_nt6"] == pytest.approx(x["dH"], rel=1e-12, abs=1e-12)
+        assert x["dH_nt3"] != x["dH"]
+        assert x["dH"] == y["dH"] and x["plaquette"] == y["plaquette"]
