@@ -80,6 +80,8 @@ def parse(argv=None):
     ap.add_argument("--compare-solvers", action="store_true",
                     help="at the end, time BiCGstab on M_oo against CG on the normal equations on the final field")
     ap.add_argument("--out", required=True)
+    ap.add_argument("--checkpoint", default=None,
+                    help="where the gauge field is saved (default <out>/U_last.npy); 16^3 x 32 is 75 MB")
     return ap.parse_args(argv)
 
 
@@ -149,6 +151,9 @@ def main(argv=None):
     from paper_1805_03560_amd import synth, whmc
 
     os.makedirs(a.out, exist_ok=True)
+    ckpt = a.checkpoint or os.path.join(a.out, "U_last.npy")
+    if os.path.dirname(ckpt):
+        os.makedirs(os.path.dirname(ckpt), exist_ok=True)
     dims = tuple(a.dims)
     V = int(np.prod(dims))
     Vh = V // 2
@@ -235,11 +240,11 @@ def main(argv=None):
         if done % 10 == 0 or done == a.ntraj:
             print(f"[ensemble] traj {traj}: P {rec['plaquette']:.5f} dH {rec['dH']:+.4f} acc {rec['accepted']} "
                   f"iters {rec['cg_iters']} {rec['seconds']:.2f}s", flush=True)
-            np.save(os.path.join(a.out, "U_last.npy"), ctx.export_gauge().cpu().numpy())
+            np.save(ckpt, ctx.export_gauge().cpu().numpy())
         if a.max_seconds is not None and time.time() - t_start > a.max_seconds:
             break
-    np.save(os.path.join(a.out, "U_last.npy"), ctx.export_gauge().cpu().numpy())
-    state = {"next_first": a.first + done, "args": vars(a)}
+    np.save(ckpt, ctx.export_gauge().cpu().numpy())
+    state = {"next_first": a.first + done, "checkpoint": ckpt, "args": vars(a)}
     if a.compare_solvers:
         _, eta, _ = draws(torch, dev, a.seed, -1, 0, 24 * Vh)
         state["solvers"] = compare_solvers(ctx, whmc, torch, eta, a.kappa)

@@ -40,6 +40,7 @@ def test_masspre_heatbath_action_force_parity(kappas, kappa, k, n_t, n_max, dims
 
     phis_ref = masspre.mp_heatbath(lat, U, list(etas), p)
     got = unpack_half(ctx, ctx.masspre_heatbath(pack_half(ctx, etas), mp, kappa, solver=SOLVER), nf)
+    got = got.reshape(nf, lat.Vh, 4, 3)     # one field unpacks without the field axis
     for f in range(nf):
         assert rel_err(got[f], phis_ref[f]) < 1e-10, f
 
@@ -101,7 +102,7 @@ def test_masspre_md_reversibility_and_dtau_scaling():
     etas = _sources(lat, 3, 5042)
     ctx = make_ctx(dims, U)
     dHs = []
-    for m in (2, 4, 8):
+    for m in (4, 8, 16):    # at m = 2 the ratio is still 5.7, not yet asymptotic
         p = masspre.MassPreParams(kappa=0.15, kappas=(0.11, 0.13), k=2, n_t=8, n_max=8, integrator="omelyan", m=m,
                                   msub=(1, 1, 2), tau=0.5)
         wp = _wp(p, whmc.OMELYAN)
@@ -111,7 +112,7 @@ def test_masspre_md_reversibility_and_dtau_scaling():
         H0 = ctx.masspre_hamiltonian(wp, pi, phi)
         ctx.masspre_md_integrate(wp, pi, phi)
         dHs.append(ctx.masspre_hamiltonian(wp, pi, phi) - H0)
-        if m == 4:
+        if m == 8:
             ctx.masspre_md_integrate(wp, -pi, phi)   # flip momenta and integrate back
             assert float(np.sum(np.abs(ctx.export_gauge().cpu().numpy() - U) ** 2)) < 1e-20
     assert 3.0 < dHs[0] / dHs[1] < 5.5 and 3.3 < dHs[1] / dHs[2] < 4.8, dHs

@@ -39,7 +39,7 @@ def test_rooted_heatbath_action_force_parity(N, ns, k, n_t, n_max, dims, gen, ka
 
     phis_ref = rooted.rooted_heatbath(lat, U, list(etas), p)
     phi, iters = ctx.rooted_heatbath(pack_half(ctx, etas), r, kappa, solver=SOLVER)
-    got = unpack_half(ctx, phi, nf)
+    got = unpack_half(ctx, phi, nf).reshape(nf, lat.Vh, 4, 3)
     assert iters >= (nf - 1)
     for f in range(nf - 1):
         assert rel_err(got[f], phis_ref[f]) < 1e-10, f
