@@ -352,23 +352,25 @@ whmc_status whmc_rooted_hamiltonian(whmc_ctx* ctx, const whmc_rooted_hmc_params*
 /* ------------------------------------------------------------------ mass preconditioning (Sec. 1, 5)
  * The fermion determinant split into factors with a pseudo-fermion each (Sec. 1), combined with the
  * kappa^(2k) filter as the conclusion proposes: with heavier hopping parameters
- * 0 < kappa_1 < ... < kappa_n < kappa_{n+1} = kappa,
- *   det M_oo(kappa) = det M_oo(kappa_1) prod_{i=1..n} det M_oo(kappa_{i+1}) / det M_oo(kappa_i).
- * Term 1 is the heaviest factor with the filter at kappa_1 (S = |M~(kappa_1)^{-1} phi_1|^2, gauge
- * action at beta + 96 kappa_1^4 for k = 2); term i + 1 is the ratio
- *   S_{i+1} = |M_oo(kappa_{i+1})^{-1} M_oo(kappa_i) phi_{i+1}|^2
- *           = |(rho_i + (1 - rho_i) M_oo(kappa_{i+1})^{-1}) phi_{i+1}|^2,   rho_i = kappa_i^2 / kappa_{i+1}^2
- * (the factors commute: both are 1 - kappa^2 H_oe H_eo).  n = 0 is the filter alone at kappa.
+ * 0 < kappa_1 < ... < kappa_n < kappa_{n+1} = kappa every factor carries the filter and one gauge
+ * term remains, that of kappa (gauge action at beta + 96 kappa^4 for k = 2):
+ *   det M_oo(kappa) = det M~(kappa_1) prod_{i=1..n} det M~(kappa_{i+1}) / det M~(kappa_i) * (gauge term).
+ * Term 1 is S_1 = |M~(kappa_1)^{-1} phi_1|^2; term i + 1 the ratio
+ *   S_{i+1} = |M~(kappa_{i+1})^{-1} M~(kappa_i) phi_{i+1}|^2 = |(sum_n b_n K^n + alpha M_oo^{-1}) phi_{i+1}|^2
+ * at kappa_{i+1}, with b_n, alpha of g(x)/(1 - x), g = (1 - rho x) exp(sum_{j<=k} (rho^j - 1) x^j / j),
+ * rho = kappa_i^2 / kappa_{i+1}^2 (all factors are functions of H_oe H_eo, so they commute); the
+ * series is truncated at n_max in the action and at n_t in the force.  Without the filter (k = 0)
+ * the ratio is rho + (1 - rho) M_oo(kappa_{i+1})^{-1}.  n = 0 is the filter alone at kappa.
  * phi and eta hold n + 1 odd-site FP64 fields back to back, term 1 first. */
 #define WHMC_MAX_MASSPRE 4
 typedef struct whmc_masspre {
   int n;                              /* heavier hopping parameters, 0 .. WHMC_MAX_MASSPRE */
   double kappas[WHMC_MAX_MASSPRE];    /* 0 < kappa_1 < ... < kappa_n < kappa */
-  whmc_filter filter;                 /* filter of the heaviest factor (k <= 2) */
+  whmc_filter filter;                 /* the filter of every factor (k <= 2) */
 } whmc_masspre;
 
-/* phi_1 = M~(kappa_1) eta_1 (series at n_max), phi_{i+1} = M_oo(kappa_i)^{-1} M_oo(kappa_{i+1}) eta_{i+1}
- * (one solve at kappa_i each).  solver may be NULL (FP64 CG to 1e-12). */
+/* phi_1 = M~(kappa_1) eta_1, phi_{i+1} = M~(kappa_i)^{-1} M~(kappa_{i+1}) eta_{i+1} (series at n_max,
+ * one solve at kappa_i each).  solver may be NULL (FP64 CG to 1e-12). */
 whmc_status whmc_masspre_heatbath(whmc_ctx* ctx, double* phi, const double* eta, const whmc_masspre* mp,
                                   double kappa, const whmc_cg_params* solver);
 

@@ -37,7 +37,7 @@ static void exp_series(int sign, int k, int n, std::vector<long double>& g) {
   }
 }
 
-static void coefficients(int k, int n, std::vector<double>& b, std::vector<double>& c, double& alpha) {
+void coefficients(int k, int n, std::vector<double>& b, std::vector<double>& c, double& alpha) {
   long double h = 0.0L;
   for (int j = 1; j <= k; ++j) h += 1.0L / j;
   alpha = (double)expl(-h);

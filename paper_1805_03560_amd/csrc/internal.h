@@ -165,6 +165,8 @@ struct MDLevel {    // one Sexton-Weingarten level: pi += scale F_l, and its sub
   std::function<whmc_status(double scale)> force;
   int nsub = 0;
 };
+// filter tables: b_0..b_n and alpha of M~^{-1}, c_0..c_n of exp(+sum_{j<=k} x^j/j)
+void coefficients(int k, int n, std::vector<double>& b, std::vector<double>& c, double& alpha);
 double delta_beta(double kappa, int k);
 whmc_cg_params default_solver();
 whmc_status solve(whmc_ctx* c, double* x, const double* rhs, double kappa, const whmc_cg_params* p, SolveLog* log);

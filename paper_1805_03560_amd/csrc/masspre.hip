@@ -1,13 +1,18 @@
 // Mass preconditioning combined with the kappa^(2k) filter (Sec. 1, 5).
 //
-// With heavier hopping parameters kappa_1 < ... < kappa_n < kappa_{n+1} = kappa the determinant is
-// det M_oo(kappa_1) prod_i det M_oo(kappa_{i+1}) / det M_oo(kappa_i).  The heaviest factor carries
-// the filter (its gauge term shifts beta by 96 kappa_1^4 for k = 2); each ratio is represented by
-// S = |M_oo(kappa_{i+1})^{-1} M_oo(kappa_i) phi|^2.  Because M_oo(kappa) = 1 - kappa^2 H_oe H_eo,
-// the two factors commute and M_oo(kappa_{i+1})^{-1} M_oo(kappa_i) = rho + (1 - rho) M_oo(kappa_{i+1})^{-1}
-// with rho = kappa_i^2 / kappa_{i+1}^2: a series action with b_0 = rho and alpha = 1 - rho at
-// kappa_{i+1}, whose action and force are the filter's series routines.  The heat bath
-// phi = M_oo(kappa_i)^{-1} M_oo(kappa_{i+1}) eta needs one solve at the heavier kappa_i.
+// With heavier hopping parameters kappa_1 < ... < kappa_n < kappa_{n+1} = kappa, every factor
+// carries the filter, M~(kappa) = M_oo(kappa) exp(sum_{j<=k} K(kappa)^j / j), and one gauge term
+// remains, that of the target kappa (beta + 96 kappa^4 for k = 2):
+//   det M_oo(kappa) = det M~(kappa_1) prod_i det M~(kappa_{i+1}) / det M~(kappa_i) exp(-sum Tr K(kappa)^j / j).
+// The heaviest field has |M~(kappa_1)^{-1} phi|^2 (the filter's action at kappa_1); each ratio has
+// S = |M~(kappa_{i+1})^{-1} M~(kappa_i) phi|^2.  All factors are functions of D = H_oe H_eo, so with
+// x = K(kappa_{i+1}) and rho = kappa_i^2 / kappa_{i+1}^2 the ratio is g(x) / (1 - x),
+// g(x) = (1 - rho x) exp(sum_{j<=k} (rho^j - 1) x^j / j): a series sum b_n x^n + alpha M_oo^{-1}
+// (alpha = g(1), b_n = sum_{m<=n} g_m - alpha) whose action and force are the filter's series
+// routines.  Its low orders cancel up to x^(k+1), which is what keeps the ratio forces small.
+// Heat bath of a ratio: phi = M~(kappa_i)^{-1} M~(kappa_{i+1}) eta, one solve at kappa_i.
+#include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "internal.h"
@@ -35,20 +40,48 @@ std::vector<double> chain(const whmc_masspre& mp, double kappa) {
   return k;
 }
 
+// b_0 .. b_n and alpha of M~(kappa_hi)^{-1} M~(kappa_lo), rho = kappa_lo^2 / kappa_hi^2, in long double
+void ratio_coefficients(double rho, int k, int n, std::vector<double>& b, double& alpha) {
+  std::vector<long double> a(n + 1, 0.0L), E(n + 1, 0.0L);
+  long double r = rho, rj = 1.0L, h = 0.0L;
+  for (int j = 1; j <= k; ++j) {
+    rj *= r;
+    h += (rj - 1.0L) / j;
+    if (j <= n) a[j] = (rj - 1.0L) / j;
+  }
+  E[0] = 1.0L;   // exp(a(x)): m E_m = sum_i i a_i E_{m-i}
+  for (int m = 1; m <= n; ++m) {
+    long double s = 0.0L;
+    for (int i = 1; i <= std::min(m, k); ++i) s += (long double)i * a[i] * E[m - i];
+    E[m] = s / m;
+  }
+  const long double al = (1.0L - r) * expl(h);
+  b.assign(n + 1, 0.0);
+  long double s = 0.0L;
+  for (int m = 0; m <= n; ++m) {
+    s += E[m] - (m >= 1 ? r * E[m - 1] : 0.0L);   // g_m of (1 - rho x) exp(a(x))
+    b[m] = (double)(s - al);
+  }
+  alpha = (double)al;
+}
+
 double* field(whmc_ctx* c, double* base, int f) { return base + (size_t)f * 24 * c->Vh; }
 const double* field(whmc_ctx* c, const double* base, int f) { return base + (size_t)f * 24 * c->Vh; }
 
 whmc_status heatbath_all(whmc_ctx* c, double* phi, const double* eta, const whmc_masspre& mp, double kappa,
                          const whmc_cg_params* sp, SolveLog* log) {
   const std::vector<double> k = chain(mp, kappa);
-  WHMC_TRY(heatbath(c, phi, eta, &mp.filter, k[0]));
+  const whmc_filter& f = mp.filter;
+  WHMC_TRY(heatbath(c, phi, eta, &f, k[0]));
   Fields F{c, (size_t)c->Vh * 192};
-  double *t, *te;
+  double* t;
   WHMC_TRY(F.get("mp_t", 0, &t));
-  WHMC_TRY(F.get("mp_te", 0, &te));
+  std::vector<double> b, cc;
+  double alpha;
+  coefficients(f.k, f.k == 0 ? 0 : f.n_max, b, cc, alpha);
   for (int i = 0; i < mp.n; ++i) {
-    WHMC_TRY(apply_Moo_f64(c, t, field(c, eta, i + 1), k[i + 1], 0, te));
-    WHMC_TRY(series_inverse(c, field(c, phi, i + 1), t, {0.0}, 1.0, k[i], sp, log));
+    WHMC_TRY(heatbath(c, t, field(c, eta, i + 1), &f, k[i + 1]));                   // M~(kappa_{i+1}) eta
+    WHMC_TRY(series_inverse(c, field(c, phi, i + 1), t, b, alpha, k[i], sp, log));  // M~(kappa_i)^{-1}
   }
   return WHMC_OK;
 }
@@ -62,8 +95,10 @@ whmc_status action_all(whmc_ctx* c, double* S, const double* phi, const whmc_mas
   WHMC_TRY(F.get("mp_z", 0, &z));
   double* sdev = c->red.result + 10;
   for (int i = 0; i < mp.n; ++i) {
-    const double rho = (k[i] / k[i + 1]) * (k[i] / k[i + 1]);
-    WHMC_TRY(series_inverse(c, z, field(c, phi, i + 1), {rho}, 1.0 - rho, k[i + 1], sp, log));
+    std::vector<double> b;
+    double alpha;
+    ratio_coefficients((k[i] / k[i + 1]) * (k[i] / k[i + 1]), mp.filter.k, mp.filter.n_max, b, alpha);
+    WHMC_TRY(series_inverse(c, z, field(c, phi, i + 1), b, alpha, k[i + 1], sp, log));
     WHMC_TRY(norm2_f64(c, z, 1, sdev));
     WHMC_TRY(read_scalar(c, sdev, &S[i + 1]));
   }
@@ -75,8 +110,10 @@ whmc_status force_term(whmc_ctx* c, double* F, const double* phi, const whmc_mas
   const std::vector<double> k = chain(mp, kappa);
   if (t == 1) return pf_force(c, F, phi, &mp.filter, k[0], sp, scale, accumulate, log);
   const int i = t - 2;
-  const double rho = (k[i] / k[i + 1]) * (k[i] / k[i + 1]);
-  return series_force(c, F, field(c, phi, i + 1), {rho}, 1.0 - rho, k[i + 1], sp, scale, accumulate, log);
+  std::vector<double> b;
+  double alpha;
+  ratio_coefficients((k[i] / k[i + 1]) * (k[i] / k[i + 1]), mp.filter.k, mp.filter.n_t, b, alpha);
+  return series_force(c, F, field(c, phi, i + 1), b, alpha, k[i + 1], sp, scale, accumulate, log);
 }
 
 whmc_status check_hmc(const whmc_masspre_hmc_params* p) {
@@ -93,7 +130,7 @@ TermAction masspre_terms(whmc_ctx* c, const whmc_masspre_hmc_params* p) {
   TermAction A;
   A.nfields = p->mp.n + 1;
   A.nterms = p->mp.n + 1;
-  A.beta_eff = p->beta + delta_beta(p->mp.n ? p->mp.kappas[0] : p->kappa, p->mp.filter.k);
+  A.beta_eff = p->beta + delta_beta(p->kappa, p->mp.filter.k);   // the gauge term of the target kappa
   A.heatbath = [=](double* phi, const double* eta, long long*) {
     return heatbath_all(c, phi, eta, p->mp, p->kappa, &p->action_solver, nullptr);
   };

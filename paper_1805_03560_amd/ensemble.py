@@ -60,6 +60,9 @@ def parse(argv=None):
     ap.add_argument("--resume", default=None, help="gauge field .npy to start from")
     ap.add_argument("--first", type=int, default=0, help="index of the first trajectory (random stream)")
     ap.add_argument("--md-tol", type=float, default=1e-10)
+    ap.add_argument("--md-prec", choices=["f64", "f32", "f16"], default="f64",
+                    help="Krylov precision of the force solves (mixed precision with FP64 reliable updates, "
+                         "12-real links; the true FP64 residual still reaches --md-tol)")
     ap.add_argument("--action-tol", type=float, default=1e-12)
     ap.add_argument("--rhs-lanes", type=int, default=2,
                     help="multi-RHS blocking of the two-rhs force solves (fixed, not autotuned, so that runs are "
@@ -168,7 +171,12 @@ def main(argv=None):
     ctx.load_gauge(torch.from_numpy(U).to(dev), unitarity_tol=1e-10)
     k, n_t, n_max = a.filter
     integ = whmc.OMELYAN if a.integrator == "omelyan" else whmc.LEAPFROG
-    md = whmc.cg_params(tol=a.md_tol, rhs_block=1, rhs_lanes=a.rhs_lanes)
+    if a.md_prec == "f64":
+        md = whmc.cg_params(tol=a.md_tol, rhs_block=1, rhs_lanes=a.rhs_lanes)
+    else:
+        prec, delta = (whmc.F32, 1e-4) if a.md_prec == "f32" else (whmc.F16, 1e-2)
+        md = whmc.cg_params(tol=a.md_tol, prec=prec, links=whmc.L12, delta=delta, rhs_block=1,
+                            rhs_lanes=a.rhs_lanes)
     act = whmc.cg_params(tol=a.action_tol)
     if a.rooted and a.masspre:
         raise SystemExit("--rooted and --masspre are separate actions")
@@ -202,8 +210,8 @@ def main(argv=None):
         pi, eta, u = draws(torch, dev, a.seed, traj, n_pi, n_eta)
         rec = {"traj": traj}
         if a.forces:
-            k_heavy = a.masspre[0] if a.masspre else a.kappa   # the filter's gauge shift sits at kappa_1
-            fg = ctx.force(ctx.half_spinor(), k, n_t, n_max, k_heavy, a.beta, flags=whmc.FORCE_GAUGE)
+            # gauge action with the filter's shift at kappa (truncations play no part in it)
+            fg = ctx.force(ctx.half_spinor(), k, 0, 0, a.kappa, a.beta, flags=whmc.FORCE_GAUGE)
             rec["F_G2"] = float(torch.dot(fg, fg))
             if a.masspre:
                 phi = ctx.masspre_heatbath(eta, p.mp, a.kappa, solver=act)

@@ -35,7 +35,8 @@ def test_ensemble_run_and_resume(tmp_path):
 
 
 ROOTED = ["--dims", "4", "4", "4", "4", "--kappa", "0.13", "--filter", "0", "12", "30", "--rooted", "2", "3", "6",
-          "--msub", "2", "1", "2", "--m", "2", "--integrator", "leapfrog", "--tau", "0.5", "--seed", "12", "--forces"]
+          "--msub", "2", "1", "2", "--m", "2", "--integrator", "leapfrog", "--tau", "0.5", "--seed", "12", "--forces",
+          "--md-prec", "f32"]
 
 
 def test_rooted_ensemble_run_and_resume(tmp_path):

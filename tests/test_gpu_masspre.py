@@ -49,11 +49,14 @@ def test_masspre_heatbath_action_force_parity(kappas, kappa, k, n_t, n_max, dims
     H_ref = masspre.mp_hamiltonian(lat, U, np.zeros((*dims, 4, 8)), phis_ref, p)
     from oracle import gauge, hpe
     chain = list(kappas) + [kappa]
-    S_G = gauge.gauge_action(lat, U, p.beta + hpe.delta_beta(chain[0], k))
+    S_G = gauge.gauge_action(lat, U, p.beta + hpe.delta_beta(kappa, k))    # the gauge term of the target kappa
     assert sum(S) == pytest.approx(H_ref - S_G, rel=1e-11)
     for i in range(len(kappas)):
-        assert S[i + 1] == pytest.approx(masspre.ratio_action(lat, U, phis_ref[i + 1], chain[i], chain[i + 1]),
-                                         rel=1e-11)
+        ref = masspre.ratio_action_series(lat, U, phis_ref[i + 1], chain[i], chain[i + 1], k, n_max)
+        assert S[i + 1] == pytest.approx(ref, rel=1e-11)
+        # the definition M~(kappa_{i+1})^{-1} M~(kappa_i) phi, up to the truncation at n_max
+        assert S[i + 1] == pytest.approx(masspre.ratio_action(lat, U, phis_ref[i + 1], chain[i], chain[i + 1], k,
+                                                              n_max), rel=1e-9)
         # heat bath sets each ratio action to the norm of its source
         assert S[i + 1] == pytest.approx(float(np.vdot(etas[i + 1], etas[i + 1]).real), rel=1e-9)
 
