@@ -401,8 +401,8 @@ def widened_16x32(whmc, torch):
     smooth field (width 0.55, seed 3200): heat bath, action and per-term force times, and one
     multi-level leapfrog / Omelyan trajectory with tau = sqrt(2) (MD solves FP64 to 1e-10, actions
     to 1e-12).  Rooted: N = 4, n = (8, 32), n_t = 160, n_max = 400, m_0, m_1, m_2 = 6, 5, 4, m = 5
-    (Table RunPoly1).  Mass preconditioning: kappa_1 = 0.14 with the kappa^4 filter (n_t = 15,
-    n_max = 29) on the heavy factor."""
+    (Table RunPoly1).  Mass preconditioning: kappa_1 = 0.14, the kappa^4 filter (n_t = 15,
+    n_max = 29) on the heavy factor and on the ratio."""
     import numpy as np
     from paper_1805_03560_amd import synth
     dims = (32, 16, 16, 16)
@@ -448,7 +448,7 @@ def widened_16x32(whmc, torch):
     eta2 = eta[: 2 * 24 * Vh]
     res = {}
     phi = ctx.masspre_heatbath(eta2, mp, kappa, solver=act)
-    for term, name in [(1, "force_heavy_kappa0.14_filtered"), (2, "force_ratio")]:
+    for term, name in [(1, "force_heavy_kappa0.14_filtered"), (2, "force_ratio_filtered")]:
         ctx.masspre_force(phi, mp, kappa, term=term, solver=md, out=F)
         res[name + "_ms"] = round(time_events(lambda: ctx.masspre_force(phi, mp, kappa, term=term, solver=md, out=F),
                                               stream, torch), 2)
