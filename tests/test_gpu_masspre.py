@@ -153,3 +153,24 @@ def test_masspre_rejects_bad_arguments():
         ctx.masspre_action(phi, whmc.masspre((0.13, 0.12)), 0.15)      # not increasing
     with pytest.raises(whmc.WhmcError):
         ctx.masspre_force(phi, whmc.masspre((0.12,)), 0.15, term=3)
+
+
+def test_masspre_four_heavier_kappas():
+    """n = WHMC_MAX_MASSPRE: four ratios, each with its own series, against the oracle."""
+    dims = (4, 4, 4, 4)
+    lat = Lattice(dims)
+    U = synth.haar_links(dims, 5070)
+    kappas, kappa = (0.09, 0.11, 0.13, 0.145), 0.156
+    p = masspre.MassPreParams(kappa=kappa, kappas=kappas, k=2, n_t=7, n_max=29, tol=1e-14)
+    etas = _sources(lat, 5, 5071)
+    ctx = make_ctx(dims, U)
+    mp = whmc.masspre(kappas, k=2, n_t=7, n_max=29)
+    phis_ref = masspre.mp_heatbath(lat, U, list(etas), p)
+    got = unpack_half(ctx, ctx.masspre_heatbath(pack_half(ctx, etas), mp, kappa, solver=SOLVER), 5)
+    for f in range(5):
+        assert rel_err(got[f], phis_ref[f]) < 1e-10, f
+    phi_b = pack_half(ctx, np.stack(phis_ref))
+    refs = masspre.mp_forces(lat, phis_ref, p)
+    for t in range(1, 6):
+        F = algebra_to_numpy(ctx, ctx.masspre_force(phi_b, mp, kappa, term=t, solver=SOLVER))
+        assert rel_err(F, refs[t](U)) < 1e-10, t

@@ -175,3 +175,34 @@ def test_rooted_rejects_bad_arguments():
     bad = whmc.rooted_hmc_params(rooted_action=r, msub=(0, 1))
     with pytest.raises(whmc.WhmcError):
         ctx.rooted_hamiltonian(bad, ctx.algebra(), phi)
+
+
+def test_rooted_four_polynomials_on_a_padded_lattice():
+    """jmax = WHMC_MAX_POLY with N = 1, on time slices of 9 x 128 sites per parity (the slice
+    schedule with idle padding workgroups) and a time extent of 2 (t + 1 = t - 1): heat bath,
+    every term of the action and the force of every term."""
+    dims = (2, 12, 12, 16)
+    lat = Lattice(dims)
+    U = synth.haar_links(dims, 4070)
+    kappa, N, ns = 0.12, 1, (1, 2, 3, 4)
+    p = rooted.RootedHMCParams(kappa=kappa, N=N, ns=ns, k=1, n_t=6, n_max=12, tol=1e-14)
+    etas = _sources(lat, len(ns) + 1, 4071)
+    ctx = make_ctx(dims, U)
+    r = whmc.rooted(N, ns, k=1, n_t=6, n_max=12)
+    phis_ref = rooted.rooted_heatbath(lat, U, list(etas), p)
+    phi, _ = ctx.rooted_heatbath(pack_half(ctx, etas), r, kappa, solver=SOLVER)
+    got = unpack_half(ctx, phi, len(ns) + 1).reshape(len(ns) + 1, lat.Vh, 4, 3)
+    for f in range(len(ns) + 1):
+        assert rel_err(got[f], phis_ref[f]) < 1e-10, f
+    phi_b = pack_half(ctx, np.stack(phis_ref))
+    S = ctx.rooted_action(phi_b, r, kappa, solver=SOLVER)
+    ps, b, al = rooted.coefficients_f64(N, ns, 1, 12)
+    for j, pj in enumerate(ps):
+        assert S[j] == pytest.approx(rooted.poly_action(lat, U, phis_ref[j], pj, kappa), rel=1e-12)
+    for term in range(1, len(ns) + 2):
+        F = algebra_to_numpy(ctx, ctx.rooted_force(phi_b, r, kappa, term=term, solver=SOLVER))
+        if term <= len(ns):
+            ref = rooted.series_force(lat, U, phis_ref[term - 1], ps[term - 1], 0.0, kappa)
+        else:
+            ref = rooted.series_force(lat, U, phis_ref[-1], b[:7], al, kappa, tol=1e-14)
+        assert rel_err(F, ref) < 1e-10, term
