@@ -369,6 +369,11 @@ typedef struct whmc_masspre {
   whmc_filter filter;                 /* the filter of every factor (k <= 2) */
 } whmc_masspre;
 
+/* Coefficient table of one ratio on the host, in extended precision: b[0..n] (n <= WHMC_ROOTED_MAX_N)
+ * and alpha of M~(kappa_{i+1})^{-1} M~(kappa_i) = sum_n b_n K^n + alpha M_oo^{-1} for
+ * rho = kappa_i^2 / kappa_{i+1}^2 in (0, 1) and filter order k in 0..2.  Needs no GPU. */
+whmc_status whmc_masspre_coefficients(double rho, int k, int n, double* b, double* alpha);
+
 /* phi_1 = M~(kappa_1) eta_1, phi_{i+1} = M~(kappa_i)^{-1} M~(kappa_{i+1}) eta_{i+1} (series at n_max,
  * one solve at kappa_i each).  solver may be NULL (FP64 CG to 1e-12). */
 whmc_status whmc_masspre_heatbath(whmc_ctx* ctx, double* phi, const double* eta, const whmc_masspre* mp,

@@ -152,6 +152,18 @@ using namespace whmc;
 
 extern "C" {
 
+whmc_status whmc_masspre_coefficients(double rho, int k, int n, double* b, double* alpha) {
+  WHMC_CHECK(rho > 0.0 && rho < 1.0, WHMC_EARG, "whmc_masspre_coefficients: rho must be in (0, 1)");
+  WHMC_CHECK(k >= 0 && k <= 2, WHMC_EUNSUP, "whmc_masspre_coefficients: filter order k must be 0, 1 or 2");
+  WHMC_CHECK(n >= 0 && n <= WHMC_ROOTED_MAX_N, WHMC_EARG, "whmc_masspre_coefficients: n must be in 0..1000");
+  std::vector<double> bb;
+  double a;
+  ratio_coefficients(rho, k, n, bb, a);
+  if (b) std::copy(bb.begin(), bb.end(), b);
+  if (alpha) *alpha = a;
+  return WHMC_OK;
+}
+
 whmc_status whmc_masspre_heatbath(whmc_ctx* c, double* phi, const double* eta, const whmc_masspre* mp, double kappa,
                                   const whmc_cg_params* solver) {
   WHMC_CHECK(c && phi && eta && phi != eta, WHMC_EARG, "whmc_masspre_heatbath: bad argument");

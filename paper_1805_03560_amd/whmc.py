@@ -172,6 +172,8 @@ _SIGS = {
     "whmc_rooted_md_integrate": ([_P, ctypes.POINTER(RootedHMCParams), _P, _P], ctypes.c_int),
     "whmc_rooted_hamiltonian": ([_P, ctypes.POINTER(RootedHMCParams), _P, _P, ctypes.POINTER(ctypes.c_double)],
                                 ctypes.c_int),
+    "whmc_masspre_coefficients": ([ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "whmc_masspre_heatbath": ([_P, _P, _P, ctypes.POINTER(MassPre), ctypes.c_double, ctypes.POINTER(CGParams)],
                               ctypes.c_int),
     "whmc_masspre_action": ([_P, ctypes.POINTER(ctypes.c_double), _P, ctypes.POINTER(MassPre), ctypes.c_double,
@@ -220,6 +222,14 @@ def filter_coefficients(k, n):
     a = ctypes.c_double()
     _check(lib().whmc_filter_coefficients(k, n, b, c, ctypes.byref(a)))
     return list(b), list(c), a.value
+
+
+def masspre_coefficients(rho, k, n):
+    """(b[0..n], alpha) of one mass-preconditioning ratio, computed by the library."""
+    b = (ctypes.c_double * (n + 1))()
+    a = ctypes.c_double()
+    _check(lib().whmc_masspre_coefficients(float(rho), int(k), int(n), b, ctypes.byref(a)))
+    return list(b), a.value
 
 
 def rooted_coefficients(r, nb):

@@ -81,3 +81,20 @@ def test_rooted_coefficients_reject_bad_input():
             whmc.rooted_coefficients(r, 10)
     with pytest.raises(whmc.WhmcError):
         whmc.rooted_coefficients(whmc.rooted(2, (8,)), 1001)
+
+
+@pytest.mark.parametrize("rho,k,n", [(0.5, 0, 10), (0.74, 1, 40), (0.8054, 2, 60), (0.3, 2, 200)])
+def test_masspre_coefficients_match_oracle(rho, k, n):
+    """the library's long-double series of g(x)/(1 - x), g = (1 - rho x) exp(sum_{j<=k} (rho^j - 1) x^j / j),
+    against the oracle's 50-digit one (pinned against dense matrix functions)."""
+    from oracle import masspre
+    b, alpha = whmc.masspre_coefficients(rho, k, n)
+    bo, ao = masspre.ratio_coefficients(rho, k, n)
+    assert alpha == pytest.approx(ao, rel=1e-15)
+    np.testing.assert_allclose(b, bo, rtol=1e-14, atol=1e-17)
+
+
+def test_masspre_coefficients_reject_bad_input():
+    for args in ((0.0, 2, 10), (1.0, 2, 10), (0.5, 3, 10), (0.5, 2, 1001)):
+        with pytest.raises(whmc.WhmcError):
+            whmc.masspre_coefficients(*args)
