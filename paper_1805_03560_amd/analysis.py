@@ -105,12 +105,31 @@ def load(path):
         return [json.loads(line) for line in f if line.strip()]
 
 
+def summarize_chains(chains, therm=0):
+    """independent chains of one action: each chain's summary, the summary of the pooled records
+    (the first `therm` trajectories of every chain dropped), and <P> with the error from the
+    spread of the chain means (which does not trust the windowed error of short chains)."""
+    out = {"chains": [summarize(c, therm) for c in chains]}
+    pooled = [r for c in chains for r in c if r["traj"] >= therm]
+    out["pooled"] = summarize(pooled)
+    means = np.array([c["plaquette"]["mean"] for c in out["chains"] if c])
+    if len(means) > 1:
+        out["plaquette_between_chains"] = {"mean": float(means.mean()),
+                                           "err": float(means.std(ddof=1) / math.sqrt(len(means))),
+                                           "n_chains": int(len(means))}
+    return out
+
+
 def main(argv=None):
-    ap = argparse.ArgumentParser(description="summarise an HMC run written by paper_1805_03560_amd.ensemble")
-    ap.add_argument("jsonl")
-    ap.add_argument("--therm", type=int, default=0, help="drop trajectories with index below this")
+    ap = argparse.ArgumentParser(description="summarise HMC runs written by paper_1805_03560_amd.ensemble; several "
+                                             "files are taken as independent chains of one action")
+    ap.add_argument("jsonl", nargs="+")
+    ap.add_argument("--therm", type=int, default=0, help="drop trajectories with index below this (per chain)")
     a = ap.parse_args(argv)
-    print(json.dumps(summarize(load(a.jsonl), a.therm), indent=1))
+    if len(a.jsonl) == 1:
+        print(json.dumps(summarize(load(a.jsonl[0]), a.therm), indent=1))
+    else:
+        print(json.dumps(summarize_chains([load(f) for f in a.jsonl], a.therm), indent=1))
     return 0
 
 

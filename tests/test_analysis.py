@@ -74,3 +74,13 @@ def test_probe_columns_are_summarised():
     assert s["probe_n_t=5"]["var_dH"] == pytest.approx(0.04)
     assert s["probe_n_t=15"]["P_acc"] == pytest.approx(0.5 * (1 + np.exp(-0.1)))
     assert list(k for k in s if k.startswith("probe")) == ["probe_n_t=5", "probe_n_t=15"]
+
+
+def test_chains_are_pooled_and_compared():
+    rng = np.random.default_rng(3)
+    chains = [[{"traj": i, "plaquette": 0.57 + 0.001 * c + 1e-4 * rng.standard_normal(), "dH": 0.1 * rng.standard_normal(),
+                "accepted": 1, "cg_iters": 1, "seconds": 0.1} for i in range(60)] for c in range(3)]
+    s = analysis.summarize_chains(chains, therm=10)
+    assert [c["n"] for c in s["chains"]] == [50, 50, 50] and s["pooled"]["n"] == 150
+    b = s["plaquette_between_chains"]
+    assert b["mean"] == pytest.approx(0.571, abs=1e-4) and b["err"] == pytest.approx(0.001 / 3 ** 0.5, rel=0.1)
