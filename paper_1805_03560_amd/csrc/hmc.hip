@@ -369,8 +369,8 @@ whmc_status term_trajectory(whmc_ctx* c, const TermAction& A, const TermMD& md, 
   WHMC_HIP(hipMemcpyAsync(pi, pi0, ab, hipMemcpyDeviceToDevice, c->stream));
   WHMC_HIP(hipMemcpyAsync(Usave, c->U18, ub, hipMemcpyDeviceToDevice, c->stream));
   long long hb_iters = 0;
-  WHMC_TRY(A.heatbath((double*)phi, eta, &hb_iters));
   SolveLog log, mdlog;
+  WHMC_TRY(A.heatbath((double*)phi, eta, &hb_iters, &log));
   double H0, H1;
   WHMC_TRY(term_hamiltonian(c, A, (double*)pi, (double*)phi, &H0, &log));
   WHMC_TRY(term_md(c, A, md, (double*)pi, (const double*)phi, &mdlog));

@@ -191,7 +191,9 @@ struct TermAction {
   int nfields = 1;          // odd-site FP64 fields in phi and eta
   int nterms = 1;           // pseudo-fermion terms
   double beta_eff = 0.0;    // gauge coupling including the filter's shift
-  std::function<whmc_status(double* phi, const double* eta, long long* iters)> heatbath;
+  // phi from the Gaussian sources eta; M_oo^dag M_oo solves go to log, other Krylov iterations
+  // (the polynomial heat bath of the rooted action) to aux_iters
+  std::function<whmc_status(double* phi, const double* eta, long long* aux_iters, SolveLog* log)> heatbath;
   std::function<whmc_status(double* S, const double* phi, SolveLog* log)> action;   // S[0 .. nterms)
   // F (or pi) += scale * force of term t (1 .. nterms); overwrite unless accumulate
   std::function<whmc_status(double* F, const double* phi, int t, double scale, int accumulate, SolveLog* log)> force;

@@ -131,8 +131,8 @@ TermAction masspre_terms(whmc_ctx* c, const whmc_masspre_hmc_params* p) {
   A.nfields = p->mp.n + 1;
   A.nterms = p->mp.n + 1;
   A.beta_eff = p->beta + delta_beta(p->kappa, p->mp.filter.k);   // the gauge term of the target kappa
-  A.heatbath = [=](double* phi, const double* eta, long long*) {
-    return heatbath_all(c, phi, eta, p->mp, p->kappa, &p->action_solver, nullptr);
+  A.heatbath = [=](double* phi, const double* eta, long long*, SolveLog* log) {
+    return heatbath_all(c, phi, eta, p->mp, p->kappa, &p->action_solver, log);
   };
   A.action = [=](double* S, const double* phi, SolveLog* log) {
     return action_all(c, S, phi, p->mp, p->kappa, &p->action_solver, log);

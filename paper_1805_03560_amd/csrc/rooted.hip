@@ -232,7 +232,7 @@ TermAction rooted_terms(whmc_ctx* c, const whmc_rooted_hmc_params* p, const Root
   A.nfields = n_fields(p->rooted);
   A.nterms = p->rooted.jmax + 1;
   A.beta_eff = p->beta + delta_beta(p->kappa, p->rooted.k);
-  A.heatbath = [=, &C](double* phi, const double* eta, long long* it) {
+  A.heatbath = [=, &C](double* phi, const double* eta, long long* it, SolveLog*) {
     return heatbath_all(c, phi, eta, p->rooted, C, p->kappa, &p->heatbath_solver, it);
   };
   A.action = [=, &C](double* S, const double* phi, SolveLog* log) {
