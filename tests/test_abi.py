@@ -98,3 +98,49 @@ def test_masspre_coefficients_reject_bad_input():
     for args in ((0.0, 2, 10), (1.0, 2, 10), (0.5, 3, 10), (0.5, 2, 1001)):
         with pytest.raises(whmc.WhmcError):
             whmc.masspre_coefficients(*args)
+
+
+def _struct_fields(text, cname):
+    """field names of `typedef struct cname {...} cname;`, in order (several names per declaration allowed)."""
+    body = re.search(r"typedef struct " + cname + r"\s*\{(.*?)\}\s*" + cname + ";", text, re.S).group(1)
+    names = []
+    for decl in (d.strip() for d in body.split(";")):
+        if decl:
+            parts = decl.split(",")
+            names.append(re.search(r"(\w+)\s*(?:\[[^\]]*\])?\s*$", parts[0]).group(1))
+            names += [re.search(r"(\w+)", q).group(1) for q in parts[1:]]
+    return names
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """size and field offsets of every parameter struct as the C compiler lays them out from
+    include/whmc.h against the binding's ctypes structures (a drifted field would pass garbage)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {
+        "whmc_cg_params": whmc.CGParams, "whmc_cg_stats": whmc.CGStats, "whmc_filter": whmc.Filter,
+        "whmc_hmc_params": whmc.HMCParams, "whmc_traj_result": whmc.TrajResult, "whmc_rooted": whmc.Rooted,
+        "whmc_rooted_hmc_params": whmc.RootedHMCParams, "whmc_masspre": whmc.MassPre,
+        "whmc_masspre_hmc_params": whmc.MassPreHMCParams,
+    }
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, py in structs.items():
+        fields = _struct_fields(text, cname)
+        assert len(fields) == len(py._fields_), (cname, fields)
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in fields:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                                check=True).stdout.split("\n") if line)
+    for cname, py in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f, (pyname, _) in zip(_struct_fields(text, cname), py._fields_):
+            assert int(got[f"{cname}.{f}"]) == getattr(py, pyname).offset, (cname, f, pyname)
