@@ -148,8 +148,23 @@ def draws(torch, dev, seed, traj, n_pi, n_eta):
     return pi, eta, u
 
 
+def check_args(a):
+    """consistency of the command line, before anything touches the GPU (SystemExit on error)."""
+    if a.rooted and a.masspre:
+        raise SystemExit("--rooted and --masspre are separate actions")
+    if a.rooted and len(a.rooted) < 1:
+        raise SystemExit("--rooted needs the root order N")
+    n_levels = (len(a.rooted) - 1 if a.rooted else len(a.masspre) if a.masspre else None)
+    if n_levels is not None and a.msub is not None and len(a.msub) != n_levels + 1:
+        raise SystemExit("--msub needs m_0 .. m_n: one more value than there are polynomials (--rooted) or "
+                         "heavier kappas (--masspre)")
+    if a.probe_nt and (a.rooted or a.masspre):
+        raise SystemExit("--probe-nt applies to the filter action only")
+
+
 def main(argv=None):
     a = parse(argv)
+    check_args(a)
     import torch
     from paper_1805_03560_amd import synth, whmc
 
@@ -178,21 +193,15 @@ def main(argv=None):
         md = whmc.cg_params(tol=a.md_tol, prec=prec, links=whmc.L12, delta=delta, rhs_block=1,
                             rhs_lanes=a.rhs_lanes)
     act = whmc.cg_params(tol=a.action_tol)
-    if a.rooted and a.masspre:
-        raise SystemExit("--rooted and --masspre are separate actions")
     if a.masspre:
         mp = whmc.masspre(a.masspre, k=k, n_t=n_t, n_max=n_max)
         msub = a.msub or [a.m0] + [1] * mp.n
-        if len(msub) != mp.n + 1:
-            raise SystemExit("--msub needs m_0 .. m_n (one more value than there are heavier kappas)")
         p = whmc.masspre_hmc_params(beta=a.beta, kappa=a.kappa, mp=mp, integrator=integ, lam=a.lam, m=a.m,
                                     msub=msub, tau=a.tau, md_solver=md, action_solver=act)
         n_fields = mp.n + 1
     elif a.rooted:
         r = whmc.rooted(a.rooted[0], a.rooted[1:], k=k, n_t=n_t, n_max=n_max)
         msub = a.msub or [a.m0] + [1] * r.jmax
-        if len(msub) != r.jmax + 1:
-            raise SystemExit("--msub needs m_0 .. m_jmax (one more value than there are polynomials)")
         p = whmc.rooted_hmc_params(beta=a.beta, kappa=a.kappa, rooted_action=r, integrator=integ, lam=a.lam, m=a.m,
                                    msub=msub, tau=a.tau, md_solver=md, action_solver=act,
                                    heatbath_solver=whmc.cg_params(tol=a.heatbath_tol))
@@ -228,8 +237,6 @@ def main(argv=None):
                 fpf = ctx.force(phi, k, n_t, n_max, a.kappa, a.beta, flags=whmc.FORCE_PF, solver=md)
                 rec["F_PF2"] = float(torch.dot(fpf, fpf))
         if a.probe_nt:
-            if a.rooted or a.masspre:
-                raise SystemExit("--probe-nt applies to the filter action only")
             probe_nt(ctx, whmc, a, p, pi, eta, rec)
         if a.masspre:
             r = ctx.masspre_trajectory(p, pi, eta, u)

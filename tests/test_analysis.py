@@ -84,3 +84,17 @@ def test_chains_are_pooled_and_compared():
     assert [c["n"] for c in s["chains"]] == [50, 50, 50] and s["pooled"]["n"] == 150
     b = s["plaquette_between_chains"]
     assert b["mean"] == pytest.approx(0.571, abs=1e-4) and b["err"] == pytest.approx(0.001 / 3 ** 0.5, rel=0.1)
+
+
+def test_ensemble_command_line_is_checked_before_the_gpu():
+    from paper_1805_03560_amd import ensemble
+    base = ["--out", "unused"]
+    ok = [["--rooted", "4", "8", "32", "--msub", "6", "5", "4"], ["--masspre", "0.14", "--msub", "6", "2"],
+          ["--probe-nt", "4", "5"], ["--rooted", "4", "8", "32"]]
+    for extra in ok:
+        ensemble.check_args(ensemble.parse(base + extra))
+    bad = [["--rooted", "4", "8", "--masspre", "0.14"], ["--rooted", "4", "8", "32", "--msub", "6", "5"],
+           ["--masspre", "0.12", "0.14", "--msub", "6", "2"], ["--rooted", "4", "8", "--probe-nt", "5"]]
+    for extra in bad:
+        with pytest.raises(SystemExit):
+            ensemble.check_args(ensemble.parse(base + extra))
