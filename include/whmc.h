@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define WHMC_ABI_VERSION 1
+#define WHMC_ABI_VERSION 2
 
 typedef enum whmc_status {
   WHMC_OK = 0,
@@ -57,7 +57,8 @@ typedef enum whmc_status {
   WHMC_ENOCONV = 3,  /* solver hit maxiter; statistics are still filled in */
   WHMC_EUNSUP = 4,   /* valid but unsupported combination (e.g. filter order k > 2) */
   WHMC_ENOTSU3 = 5,  /* gauge field not unitary / det != 1 within the given tolerance */
-  WHMC_ESTATE = 6    /* call out of order (e.g. no gauge field loaded yet) */
+  WHMC_ESTATE = 6,   /* call out of order (e.g. no gauge field loaded yet) */
+  WHMC_ENONFINITE = 7 /* a NaN or infinity in an input or in a solver's scalars (e.g. a NaN in phi) */
 } whmc_status;
 
 typedef enum whmc_prec { WHMC_F64 = 0, WHMC_F32 = 1, WHMC_F16 = 2 } whmc_prec;
@@ -78,6 +79,17 @@ const char* whmc_last_error(void);
 whmc_status whmc_create(whmc_ctx** ctx, const int dims[4], int device, void* stream);
 void whmc_destroy(whmc_ctx* ctx);
 whmc_status whmc_set_stream(whmc_ctx* ctx, void* stream);
+
+/* Context options (values are 64-bit integers):
+ *   WHMC_OPT_STREAM_THRESHOLD  link arrays larger than this many bytes are read with non-temporal
+ *                              (streaming) loads in every stencil, solver and force kernel, so that
+ *                              they do not evict neighbour spinors from the caches; -1 = never,
+ *                              0 = always.  Default 128 MiB (streaming pays once a link array no
+ *                              longer fits the caches; smaller lattices run faster without it).
+ * EARG for an unknown option or a value below -1. */
+#define WHMC_OPT_STREAM_THRESHOLD 1
+whmc_status whmc_set_option(whmc_ctx* ctx, int option, long long value);
+whmc_status whmc_get_option(const whmc_ctx* ctx, int option, long long* value);
 
 /* Bytes of one field of the given kind in the whmc layout:
  * kind 0 = half spinor, 1 = full spinor, 2 = algebra field (prec ignored), 3 = canonical gauge. */
@@ -132,8 +144,17 @@ whmc_status whmc_autotune(whmc_ctx* ctx, int prec, int links, int nrhs, int* rhs
  * odd-site half fields (Sec. 2.2).  Uses context scratch for the even-site intermediate. */
 whmc_status whmc_apply_Moo(whmc_ctx* ctx, double* out, const double* in, double kappa, int dagger);
 
-/* out_r = M_oo(kappa_r)^dag M_oo(kappa_r) in_r for r < nrhs, FP64, odd-site half fields. */
-whmc_status whmc_apply_MdagM(whmc_ctx* ctx, double* out, const double* in, const double* kappas, int nrhs);
+/* Full-lattice fermion matrix of Sec. 1, M = 1 - kappa H (dagger = 1: M^dag = gamma_5 M gamma_5),
+ * on full spinors (even half then odd half, whmc layout, FP64, 18-real links).  in and out must
+ * not overlap. */
+whmc_status whmc_apply_M(whmc_ctx* ctx, double* out, const double* in, double kappa, int dagger);
+
+/* out_r = A(kappa_r) in_r for r < nrhs, FP64, with
+ *   eo = 1: A = M_oo^dag M_oo on odd-site half fields (even/odd form, Sec. 2.2),
+ *   eo = 0: A = M^dag M on full spinors, M = 1 - kappa H (Sec. 1).
+ * The nrhs fields are consecutive (half or full fields).  in and out must not overlap.
+ * Uses context scratch for the intermediates (allocated on first use). */
+whmc_status whmc_apply_MdagM(whmc_ctx* ctx, double* out, const double* in, const double* kappas, int nrhs, int eo);
 
 /* ------------------------------------------------------------------ solver (Sec. 1, 4)
  * Solve M_oo(kappa_r)^dag M_oo(kappa_r) x_r = b_r (odd-site half fields, FP64 whmc layout) by CG
@@ -169,6 +190,15 @@ typedef struct whmc_cg_stats {
 
 whmc_status whmc_cg_solve(whmc_ctx* ctx, double* x, const double* b, const double* kappas, int nrhs,
                           const whmc_cg_params* params, whmc_cg_stats* stats);
+
+/* Solve M^dag M x = b on the full lattice (M = 1 - kappa H, Sec. 1; full spinors, whmc layout) by
+ * FP64 CG from x = 0 until the true residual |b - A x| / |b| <= params->tol.  params->prec must be
+ * WHMC_F64 (else WHMC_EUNSUP); params->links selects 18- or 12-real links; maxiter and check_every
+ * as for whmc_cg_solve (one iteration applies H four times, two launches of both parities).
+ * stats (may be NULL) receives one entry.  ENOCONV if tol is not reached, ENONFINITE if b or an
+ * iterate is not finite. */
+whmc_status whmc_cg_solve_full(whmc_ctx* ctx, double* x, const double* b, double kappa, const whmc_cg_params* params,
+                               whmc_cg_stats* stats);
 
 /* Solve M_oo(kappa) x = b (dagger = 0) or M_oo(kappa)^dag x = b (dagger = 1) for one odd-site half
  * field (FP64 whmc layout) by BiCGstab, the Krylov solver the paper uses (Sec. 4), from x = 0 until
@@ -216,6 +246,16 @@ whmc_status whmc_plaquette(whmc_ctx* ctx, double* plaq);
 #define WHMC_FORCE_ACCUMULATE 4
 whmc_status whmc_force(whmc_ctx* ctx, double* F, const double* phi, const whmc_filter* f, double kappa,
                        double beta, const whmc_cg_params* solver, int flags);
+
+/* Full-lattice pseudo-fermion action and force without even/odd preconditioning (Sec. 1):
+ * S_PF = |M^{-1} phi|^2 for a full spinor phi, force from delta S = -X^dag delta M Y + h.c. with
+ * X = (M M^dag)^{-1} phi = gamma_5 (M^dag M)^{-1} gamma_5 phi (one full-lattice CG) and Y = M^dag X.
+ * whmc_force_full flags as for whmc_force (WHMC_FORCE_GAUGE adds the gauge force at beta, no shift).
+ * solver may be NULL (FP64 CG to 1e-12). */
+whmc_status whmc_action_full(whmc_ctx* ctx, double* S_PF, const double* phi, double kappa,
+                             const whmc_cg_params* solver);
+whmc_status whmc_force_full(whmc_ctx* ctx, double* F, const double* phi, double kappa, double beta,
+                            const whmc_cg_params* solver, int flags);
 
 /* Molecular-dynamics primitives (Sec. 1, with the step conventions of this library):
  * T step  U_{x,mu} <- exp(eps Pi_{x,mu}) U_{x,mu}  (exact SU(3) exponential, FP64 master copy;

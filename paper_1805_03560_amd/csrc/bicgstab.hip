@@ -282,6 +282,7 @@ static whmc_status bicgstab_f64(whmc_ctx* c, double* x, const double* b, double 
   WHMC_TRY(norm2_f64(c, b, 1, c->red.result + 3));
   double bb;
   WHMC_TRY(read_scalar(c, c->red.result + 3, &bb));
+  WHMC_CHECK(std::isfinite(bb), WHMC_ENONFINITE, "whmc_bicgstab_solve: the right-hand side is not finite");
   WHMC_TRY(zero_bytes(c, x, hb));
   st->iters = 0;
   st->reliable_updates = 0;
@@ -331,6 +332,7 @@ static whmc_status bicgstab_f64(whmc_ctx* c, double* x, const double* b, double 
     WHMC_TRY(norm2_f64(c, (double*)r, 1, c->red.result + 2));
     WHMC_TRY(read_scalar(c, c->red.result + 2, &rr));
     st->true_residual = std::sqrt(rr / bb);
+    WHMC_CHECK(std::isfinite(st->true_residual), WHMC_ENONFINITE, "whmc_bicgstab_solve: the residual is not finite");
     if (st->true_residual <= prm->tol) {
       st->converged = 1;
       break;

@@ -308,6 +308,7 @@ static whmc_status cg_f64(whmc_ctx* c, double* x, const double* b, double kappa,
   WHMC_TRY(norm2_f64(c, b, 1, c->red.result + 3));
   double bb;
   WHMC_TRY(read_scalar(c, c->red.result + 3, &bb));
+  WHMC_CHECK(std::isfinite(bb), WHMC_ENONFINITE, "cg_solve: the right-hand side is not finite");
   WHMC_TRY(zero_bytes(c, x, hb));
   st->iters = 0;
   st->reliable_updates = 0;
@@ -351,6 +352,7 @@ static whmc_status cg_f64(whmc_ctx* c, double* x, const double* b, double kappa,
     double rel;
     WHMC_TRY(true_residual(c, (double*)r, x, b, kappa, (double*)te, (double*)to, bb, &rel));
     st->true_residual = rel;
+    WHMC_CHECK(std::isfinite(rel), WHMC_ENONFINITE, "cg_solve: the residual is not finite");
     if (rel <= prm->tol) {
       st->converged = 1;
       break;
@@ -385,6 +387,7 @@ static whmc_status cg_mixed(whmc_ctx* c, double* x, const double* b, double kapp
   WHMC_TRY(norm2_f64(c, b, 1, c->red.result + 3));
   double bb;
   WHMC_TRY(read_scalar(c, c->red.result + 3, &bb));
+  WHMC_CHECK(std::isfinite(bb), WHMC_ENONFINITE, "cg_solve: the right-hand side is not finite");
   WHMC_TRY(zero_bytes(c, x, hb));
   st->iters = 0;
   st->reliable_updates = 0;
@@ -419,6 +422,7 @@ static whmc_status cg_mixed(whmc_ctx* c, double* x, const double* b, double kapp
     WHMC_HIP(hipGetLastError());
     WHMC_TRY(true_residual(c, (double*)r64, x, b, kappa, (double*)te, (double*)to, bb, &rel));
     st->reliable_updates += 1;
+    WHMC_CHECK(std::isfinite(rel), WHMC_ENONFINITE, "cg_solve: the residual is not finite");
     if (rel <= prm->tol) {
       st->converged = 1;
       break;
@@ -438,6 +442,8 @@ static whmc_status cg_mixed(whmc_ctx* c, double* x, const double* b, double kapp
     WHMC_HIP(hipGetLastError());
     WHMC_TRY(true_residual(c, (double*)r64, x, b, kappa, (double*)te, (double*)to, bb, &rel));
     st->converged = rel <= prm->tol;
+    st->true_residual = rel;
+    WHMC_CHECK(std::isfinite(rel), WHMC_ENONFINITE, "cg_solve: the residual is not finite");
   }
   st->true_residual = rel;
   st->iters = iters;

@@ -656,16 +656,49 @@ whmc_status whmc_apply_Moo(whmc_ctx* c, double* out, const double* in, double ka
   return apply_Moo_f64(c, out, in, kappa, dagger ? 1 : 0, (double*)tmp);
 }
 
-whmc_status whmc_apply_MdagM(whmc_ctx* c, double* out, const double* in, const double* kappas, int nrhs) {
+whmc_status whmc_apply_MdagM(whmc_ctx* c, double* out, const double* in, const double* kappas, int nrhs, int eo) {
   WHMC_CHECK(c && out && in && kappas && nrhs >= 1, WHMC_EARG, "whmc_apply_MdagM: bad argument");
   WHMC_CHECK(out != in, WHMC_EARG, "whmc_apply_MdagM: in and out must differ");
+  WHMC_CHECK(eo == 0 || eo == 1, WHMC_EARG, "whmc_apply_MdagM: eo must be 0 (full lattice) or 1 (even/odd)");
+  WHMC_CHECK(c->gauge_loaded, WHMC_ESTATE, "no gauge field loaded");
+  const size_t hb = (size_t)c->Vh * 192;
+  if (!eo) {
+    void* tf;
+    WHMC_TRY(workspace(c, "mdm_tmp_full", 2 * hb, &tf));
+    for (int r = 0; r < nrhs; ++r)
+      WHMC_TRY(apply_MdagM_full(c, out + (size_t)r * 48 * c->Vh, in + (size_t)r * 48 * c->Vh, kappas[r], (double*)tf));
+    return WHMC_OK;
+  }
   void *te, *to;
-  WHMC_TRY(workspace(c, "mdm_tmp_even", (size_t)c->Vh * 192, &te));
-  WHMC_TRY(workspace(c, "mdm_tmp_odd", (size_t)c->Vh * 192, &to));
+  WHMC_TRY(workspace(c, "mdm_tmp_even", hb, &te));
+  WHMC_TRY(workspace(c, "mdm_tmp_odd", hb, &to));
   for (int r = 0; r < nrhs; ++r)
     WHMC_TRY(apply_MdagM_f64(c, out + (size_t)r * 24 * c->Vh, in + (size_t)r * 24 * c->Vh, kappas[r], (double*)te,
                              (double*)to));
   return WHMC_OK;
+}
+
+whmc_status whmc_set_option(whmc_ctx* c, int option, long long value) {
+  WHMC_CHECK(c, WHMC_EARG, "whmc_set_option: null context");
+  switch (option) {
+    case WHMC_OPT_STREAM_THRESHOLD:
+      WHMC_CHECK(value >= -1, WHMC_EARG, "whmc_set_option: the stream threshold must be >= -1");
+      c->stream_threshold = value;
+      return WHMC_OK;
+    default:
+      set_error("whmc_set_option: unknown option " + std::to_string(option));
+      return WHMC_EARG;
+  }
+}
+
+whmc_status whmc_get_option(const whmc_ctx* c, int option, long long* value) {
+  WHMC_CHECK(c && value, WHMC_EARG, "whmc_get_option: null argument");
+  switch (option) {
+    case WHMC_OPT_STREAM_THRESHOLD: *value = c->stream_threshold; return WHMC_OK;
+    default:
+      set_error("whmc_get_option: unknown option " + std::to_string(option));
+      return WHMC_EARG;
+  }
 }
 
 whmc_status whmc_pack_algebra(whmc_ctx* c, double* dst, const double* src) {

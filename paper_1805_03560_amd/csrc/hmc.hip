@@ -376,7 +376,8 @@ whmc_status term_trajectory(whmc_ctx* c, const TermAction& A, const TermMD& md, 
   WHMC_TRY(term_md(c, A, md, (double*)pi, (const double*)phi, &mdlog));
   WHMC_TRY(term_hamiltonian(c, A, (double*)pi, (double*)phi, &H1, &log));
   const double dH = H1 - H0;
-  const bool acc = u < std::exp(-dH);
+  const bool finite = std::isfinite(dH);
+  const bool acc = finite && u < std::exp(-dH);
   if (!acc) {
     WHMC_HIP(hipMemcpyAsync(c->U18, Usave, ub, hipMemcpyDeviceToDevice, c->stream));
     WHMC_TRY(gauge_changed(c));
@@ -392,6 +393,7 @@ whmc_status term_trajectory(whmc_ctx* c, const TermAction& A, const TermMD& md, 
   res->n_solves = log.n + mdlog.n;
   res->poly_iters = hb_iters;
   res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  WHMC_CHECK(finite, WHMC_ENONFINITE, "trajectory: dH is not finite; the gauge field was restored");
   return WHMC_OK;
 }
 
@@ -525,7 +527,8 @@ whmc_status whmc_hmc_trajectory(whmc_ctx* c, const whmc_hmc_params* p, const dou
   WHMC_TRY(filter_md(c, p, (double*)pi, (const double*)phi, &mdlog));
   WHMC_TRY(hamiltonian(c, p, (double*)pi, (double*)phi, &H1, &log));
   const double dH = H1 - H0;
-  const bool acc = u < std::exp(-dH);
+  const bool finite = std::isfinite(dH);
+  const bool acc = finite && u < std::exp(-dH);
   if (!acc) {
     WHMC_HIP(hipMemcpyAsync(c->U18, Usave, ub, hipMemcpyDeviceToDevice, c->stream));
     WHMC_TRY(gauge_changed(c));
@@ -541,6 +544,7 @@ whmc_status whmc_hmc_trajectory(whmc_ctx* c, const whmc_hmc_params* p, const dou
   res->n_solves = log.n + mdlog.n;
   res->poly_iters = 0;
   res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  WHMC_CHECK(finite, WHMC_ENONFINITE, "trajectory: dH is not finite; the gauge field was restored");
   return WHMC_OK;
 }
 

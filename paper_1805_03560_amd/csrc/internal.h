@@ -84,8 +84,8 @@ struct whmc_ctx {
   whmc::CGScalars* scal_host = nullptr;  // pinned mirror
   double* host_pinned = nullptr;     // small pinned buffer for scalar read-back
   // cache policy: stream (non-temporal) link loads when the link array of a format is larger
-  // than stream_threshold bytes; -1 = never, 0 = always.  Set by the heuristic in whmc_create or
-  // by whmc_autotune.
+  // than stream_threshold bytes; -1 = never, 0 = always.  Default 128 MiB; callers change it with
+  // whmc_set_option(WHMC_OPT_STREAM_THRESHOLD).
   long long stream_threshold = 128LL << 20;
   bool stream_links(int prec, int links) const {
     if (stream_threshold < 0) return false;
@@ -129,6 +129,9 @@ whmc_status apply_MdagM_f64(whmc_ctx* c, double* out, const double* in, double k
                             double* tmp_odd);
 whmc_status apply_K_f64(whmc_ctx* c, double* out, const double* in, double kappa, int dagger, double* even_out,
                         const double* x, double a);   // out = a x + K^(dag) in; even_out = H_eo^(dag) in
+// full lattice (full spinors = even half, odd half): out = M in or M^dag in, M = 1 - kappa H (full.hip)
+whmc_status apply_M_full(whmc_ctx* c, double* out, const double* in, double kappa, int dagger);
+whmc_status apply_MdagM_full(whmc_ctx* c, double* out, const double* in, double kappa, double* tmp_full);
 
 // ---- solvers (cg.hip)
 whmc_status cg_solve(whmc_ctx* c, double* x, const double* b, const double* kappas, int nrhs,

@@ -767,7 +767,11 @@ whmc_status cg_solve_multi(whmc_ctx* c, double* x, const double* b, const double
   WHMC_HIP(hipMemcpyAsync(c->host_pinned + 16, c->red.result + 16, nrhs * sizeof(double), hipMemcpyDeviceToHost,
                           c->stream));
   WHMC_HIP(hipStreamSynchronize(c->stream));
-  for (int r = 0; r < nrhs; ++r) bb[r] = c->host_pinned[16 + r];
+  for (int r = 0; r < nrhs; ++r) {
+    bb[r] = c->host_pinned[16 + r];
+    WHMC_CHECK(std::isfinite(bb[r]), WHMC_ENONFINITE,
+               "multi-RHS CG: right-hand side " + std::to_string(r) + " is not finite");
+  }
   WHMC_TRY(zero_bytes(c, x, hb * nrhs));
   // sloppy (or FP64) copies: r = b, p = b, x_s = 0
   if (mixed) {
@@ -902,6 +906,9 @@ whmc_status cg_solve_multi(whmc_ctx* c, double* x, const double* b, const double
       st[r].true_residual = rel_final[r];
       st[r].seconds = secs;
     }
+  for (int r = 0; r < nrhs; ++r)
+    WHMC_CHECK(std::isfinite(rel_final[r]), WHMC_ENONFINITE,
+               "multi-RHS CG: the residual of right-hand side " + std::to_string(r) + " is not finite");
   if (!all) {
     set_error("multi-RHS CG: not every right-hand side reached the tolerance");
     return WHMC_ENOCONV;

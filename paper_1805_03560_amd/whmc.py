@@ -20,7 +20,8 @@ F64, F32, F16 = 0, 1, 2
 L12, L18 = 12, 18
 LEAPFROG, OMELYAN = 0, 1
 FORCE_PF, FORCE_GAUGE, FORCE_ACCUMULATE = 1, 2, 4
-_STATUS = {0: "OK", 1: "EARG", 2: "EHIP", 3: "ENOCONV", 4: "EUNSUP", 5: "ENOTSU3", 6: "ESTATE"}
+_STATUS = {0: "OK", 1: "EARG", 2: "EHIP", 3: "ENOCONV", 4: "EUNSUP", 5: "ENOTSU3", 6: "ESTATE", 7: "ENONFINITE"}
+OPT_STREAM_THRESHOLD = 1
 _HALF_BYTES = {F64: 192, F32: 96, F16: 52}
 
 
@@ -123,6 +124,8 @@ _SIGS = {
     "whmc_create": ([ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int), ctypes.c_int, _P], ctypes.c_int),
     "whmc_destroy": ([_P], None),
     "whmc_set_stream": ([_P, _P], ctypes.c_int),
+    "whmc_set_option": ([_P, ctypes.c_int, ctypes.c_longlong], ctypes.c_int),
+    "whmc_get_option": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
     "whmc_field_bytes": ([_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "whmc_load_gauge": ([_P, _P, ctypes.c_double], ctypes.c_int),
     "whmc_export_gauge": ([_P, _P], ctypes.c_int),
@@ -139,7 +142,14 @@ _SIGS = {
                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "whmc_bicgstab_solve": ([_P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.POINTER(CGParams),
                              ctypes.POINTER(CGStats)], ctypes.c_int),
-    "whmc_apply_MdagM": ([_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int], ctypes.c_int),
+    "whmc_apply_MdagM": ([_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "whmc_apply_M": ([_P, _P, _P, ctypes.c_double, ctypes.c_int], ctypes.c_int),
+    "whmc_cg_solve_full": ([_P, _P, _P, ctypes.c_double, ctypes.POINTER(CGParams), ctypes.POINTER(CGStats)],
+                           ctypes.c_int),
+    "whmc_action_full": ([_P, ctypes.POINTER(ctypes.c_double), _P, ctypes.c_double, ctypes.POINTER(CGParams)],
+                         ctypes.c_int),
+    "whmc_force_full": ([_P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.POINTER(CGParams), ctypes.c_int],
+                        ctypes.c_int),
     "whmc_cg_solve": ([_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.POINTER(CGParams),
                        ctypes.POINTER(CGStats)], ctypes.c_int),
     "whmc_filter_coefficients": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -365,12 +375,49 @@ class Context:
         _check(lib().whmc_apply_Moo(self._h, _ptr(out), _ptr(inp), kappa, int(dagger)))
         return out
 
-    def apply_MdagM(self, inp, kappas, out=None):
+    def apply_MdagM(self, inp, kappas, out=None, eo=True):
+        """M_oo^dag M_oo on odd-site half fields (eo=True) or M^dag M on full spinors (eo=False)."""
         kappas = [float(k) for k in (kappas if hasattr(kappas, "__len__") else [kappas])]
         n = len(kappas)
-        out = self.half_spinor(F64, n) if out is None else out
-        _check(lib().whmc_apply_MdagM(self._h, _ptr(out), _ptr(inp), (ctypes.c_double * n)(*kappas), n))
+        out = self.half_spinor(F64, n if eo else 2 * n) if out is None else out
+        _check(lib().whmc_apply_MdagM(self._h, _ptr(out), _ptr(inp), (ctypes.c_double * n)(*kappas), n, int(bool(eo))))
         return out
+
+    def apply_M(self, inp, kappa, dagger=False, out=None):
+        """full-lattice M = 1 - kappa H (or M^dag) on a full spinor"""
+        out = self.full_spinor() if out is None else out
+        _check(lib().whmc_apply_M(self._h, _ptr(out), _ptr(inp), float(kappa), int(bool(dagger))))
+        return out
+
+    def cg_solve_full(self, b, kappa, params=None, x=None, raise_on_noconv=True):
+        """x = (M^dag M)^{-1} b on the full lattice, FP64 CG"""
+        params = params or cg_params()
+        x = self.full_spinor() if x is None else x
+        st = CGStats()
+        rc = lib().whmc_cg_solve_full(self._h, _ptr(x), _ptr(b), float(kappa), ctypes.byref(params), ctypes.byref(st))
+        if rc != 0 and (rc != 3 or raise_on_noconv):
+            _check(rc)
+        return x, st.as_dict()
+
+    def action_full(self, phi, kappa, solver=None):
+        s = ctypes.c_double()
+        _check(lib().whmc_action_full(self._h, ctypes.byref(s), _ptr(phi), float(kappa),
+                                      ctypes.byref(solver) if solver is not None else None))
+        return s.value
+
+    def force_full(self, phi, kappa, beta=0.0, flags=FORCE_PF, solver=None, out=None):
+        out = self.algebra() if out is None else out
+        _check(lib().whmc_force_full(self._h, _ptr(out), _ptr(phi), float(kappa), float(beta),
+                                     ctypes.byref(solver) if solver is not None else None, int(flags)))
+        return out
+
+    def set_option(self, option, value):
+        _check(lib().whmc_set_option(self._h, int(option), int(value)))
+
+    def get_option(self, option):
+        v = ctypes.c_longlong()
+        _check(lib().whmc_get_option(self._h, int(option), ctypes.byref(v)))
+        return v.value
 
     def cg_solve(self, b, kappas, params=None, x=None, raise_on_noconv=True):
         kappas = [float(k) for k in (kappas if hasattr(kappas, "__len__") else [kappas])]

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     L = ctypes.CDLL(whmc.LIB_PATH)
     missing = [n for n in declared_functions() if not hasattr(L, n)]
     assert not missing, missing
-    assert whmc.lib().whmc_abi_version() == 1
+    assert whmc.lib().whmc_abi_version() == 2
 
 
 @pytest.mark.parametrize("k,n", [(0, 5), (1, 19), (2, 29), (2, 60)])

@@ -51,4 +51,4 @@ def test_autograd_gradient_at_zero_is_the_oracle_force():
     assert float(S) == pytest.approx(hpe.filtered_action(lat, U, phi, 0.156, 2, 5, tol=1e-14), rel=1e-11)
     S.backward()
     ref = hpe.filtered_force(lat, U, phi, 0.156, 2, 5, tol=1e-14)
-    assert rel_err(algebra_to_numpy(ctx, omega.grad), ref) < 1e-10
+    assert rel_err(algebra_to_numpy(ctx, omega.grad), ref) < 1e-12

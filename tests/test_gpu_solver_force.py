@@ -1,8 +1,9 @@
 """GPU parity of the solvers, actions, forces and the HMC trajectory against the oracle.
 
 Tolerances: operator applications 1e-12 relative; solves are run to 1e-13/1e-14 on both sides,
-so solutions agree to ~cond(A) x 1e-13 (cond ~ 10-100 on these fields); forces that go through
-solves to 1e-10 relative; mixed-precision solves must reach the same 1e-10 true FP64 residual."""
+so solutions agree to ~cond(A) x 1e-13 (cond ~ 10-100 on these fields); forces, actions and the
+trajectory, whose solves run to 1e-14 on both sides, to 1e-12 relative; mixed-precision solves
+must reach the same 1e-10 true FP64 residual."""
 import functools
 
 import numpy as np
@@ -87,7 +88,8 @@ def test_plaquette_and_gauge_force_parity():
     assert sg == pytest.approx(gauge.gauge_action(lat, U, 5.6 + 96 * 0.156 ** 4), rel=1e-13)
 
 
-@pytest.mark.parametrize("k,n_t,n_max", [(0, 0, 0), (1, 5, 19), (2, 7, 29), (2, 0, 12)])
+# (2, 29, 29): 30 (X, Y) pairs, two launches of the pair kernel (24 pairs each), the second accumulating
+@pytest.mark.parametrize("k,n_t,n_max", [(0, 0, 0), (1, 5, 19), (2, 7, 29), (2, 0, 12), (2, 29, 29)])
 def test_filtered_action_force_heatbath_parity(k, n_t, n_max):
     dims = (4, 4, 4, 4)
     lat = Lattice(dims)
@@ -104,7 +106,7 @@ def test_filtered_action_force_heatbath_parity(k, n_t, n_max):
     assert spf == pytest.approx(hpe.filtered_action(lat, U, phi_ref, kappa, k, n_max, tol=1e-14), rel=1e-11)
     F = ctx.force(phi_b, k, n_t, n_max, kappa, 5.6, flags=whmc.FORCE_PF, solver=solver)
     ref = hpe.filtered_force(lat, U, phi_ref, kappa, k, n_t, tol=1e-14)
-    assert rel_err(algebra_to_numpy(ctx, F), ref) < 1e-10
+    assert rel_err(algebra_to_numpy(ctx, F), ref) < 1e-12
 
 
 def test_unfiltered_force_matches_plain_eo_force():
@@ -115,7 +117,7 @@ def test_unfiltered_force_matches_plain_eo_force():
     phi = synth.gaussian_spinor(lat.Vh, 2061)
     ctx = make_ctx(dims, U)
     F = ctx.force(pack_half(ctx, phi), 0, 0, 0, kappa, 5.6, solver=whmc.cg_params(tol=1e-14))
-    assert rel_err(algebra_to_numpy(ctx, F), force.pf_force_eo(lat, U, phi, kappa, tol=1e-14)) < 1e-10
+    assert rel_err(algebra_to_numpy(ctx, F), force.pf_force_eo(lat, U, phi, kappa, tol=1e-14)) < 1e-12
 
 
 @pytest.mark.parametrize("integrator,k,n_t,n_max", [("leapfrog", 0, 0, 0), ("omelyan", 2, 5, 12)])
@@ -135,10 +137,10 @@ def test_hmc_trajectory_parity(integrator, k, n_t, n_max):
                          md_solver=solver, action_solver=solver)
     res = ctx.hmc_trajectory(wp, ctx.pack_algebra(to_dev(pi)), pack_half(ctx, eta), 0.5)
     assert res["H0"] == pytest.approx(ref["H0"], rel=1e-12)
-    assert res["dH"] == pytest.approx(ref["dH"], abs=1e-8)
+    assert res["dH"] == pytest.approx(ref["dH"], abs=1e-9)
     assert bool(res["accepted"]) == ref["accepted"]
     U_gpu = ctx.export_gauge().cpu().numpy()
-    assert rel_err(U_gpu, ref["U"]) < 1e-10
+    assert rel_err(U_gpu, ref["U"]) < 1e-12
 
 
 def test_md_reversibility_and_dtau_scaling():
@@ -187,7 +189,7 @@ def test_pf_force_parity_padded_lattice():
     phi = synth.gaussian_spinor(lat.Vh, 2111)
     ctx = make_ctx(dims, U)
     F = ctx.force(pack_half(ctx, phi), 0, 0, 0, kappa, 5.6, solver=whmc.cg_params(tol=1e-14))
-    assert rel_err(algebra_to_numpy(ctx, F), force.pf_force_eo(lat, U, phi, kappa, tol=1e-14)) < 1e-10
+    assert rel_err(algebra_to_numpy(ctx, F), force.pf_force_eo(lat, U, phi, kappa, tol=1e-14)) < 1e-12
 
 
 @pytest.mark.parametrize("prec", [whmc.F64, whmc.F16])
