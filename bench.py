@@ -93,6 +93,12 @@ def main():
         ctx.apply_H(psi[k & 1], 0, out=t_e)              # t_e = H_eo psi_o
         ctx.apply_H(t_e, 1, out=psi[(k + 1) & 1])        # psi_o' = H_oe t_e
 
+    # setup: the autotuner picks the workgroup schedule of the stencil kernels (time-slice ranges per
+    # XCD, or time slabs worked through in chunks of a given size) by timing the same hop pair
+    sched, chunk, tuned_us = ctx.autotune_hop()
+    log(f"[bench] stencil schedule: {'slice ranges' if sched == 0 else f'time slabs, chunks of {chunk} blocks'} "
+        f"({tuned_us:.1f} us per hop while tuning)")
+
     # ------------------------------------------------------------ timed region: apply_H FP64
     for k in range(args.warmup):
         step(k)
@@ -123,12 +129,14 @@ def main():
                    "lattice_t_z_y_x": list(DIMS), "sites": V, "kappa": KAPPA},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(bytes_per_launch)},
+        "stencil_schedule": {"schedule": sched, "chunk_blocks": chunk, "tuned_us_per_hop": round(tuned_us, 1)},
     }
 
     if not args.no_extras:
         result.update(extras(ctx, whmc, torch, np, stream, Vh))
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline()
+        it16 = result.get("cg_16x32_fp64", {}).get("kappa0.156", {}).get("iters")
+        result["cpu_baseline"] = cpu_baseline(it16)
     ctx.close()
     print(json.dumps(result), flush=True)
 
@@ -177,28 +185,17 @@ def extras(ctx, whmc, torch, np, stream, Vh):
                                      "GBps_960B_per_site": round(960 * 2 * Vh / (ms * 1e-3) / 1e9, 1),
                                      "GBps_1536B_per_site": round(1536 * 2 * Vh / (ms * 1e-3) / 1e9, 1)}
     log(f"[bench] full-lattice H FP64: {out['full_lattice_H_f64_l18']}")
-    # hop throughput of every storage format: one H_eo launch repeated on the same input (that
-    # input can stay in the Infinity Cache), algorithmic bytes of that format
-    fmt = {}
-    x64 = ctx.pack_spinor(torch.from_numpy(synth.gaussian_spinor(Vh, 3002)).to(ctx.device), 0)
-    for (p, pn), links in [((whmc.F64, "f64"), 18), ((whmc.F64, "f64"), 12), ((whmc.F32, "f32"), 18),
-                           ((whmc.F32, "f32"), 12), ((whmc.F16, "f16"), 12)]:
-        xin = x64 if p == whmc.F64 else ctx.convert_spinor(x64, whmc.F64, p)
-        o = ctx.half_spinor(p)
-        ctx.apply_H(xin, 0, prec=p, links=links, out=o)
-        ms = time_events(lambda: ctx.apply_H(xin, 0, prec=p, links=links, out=o), stream, torch, reps=20)
-        gbs = BYTES_PER_SITE[(pn, links)] * Vh / (ms * 1e-3) / 1e9
-        fmt[f"{pn}_l{links}"] = {"us_per_hop": round(ms * 1e3, 1), "GBps": round(gbs, 1),
-                                 "frac_hbm": round(gbs / HBM_PEAK_GBS, 3)}
-        log(f"[bench] hop {pn}-{links}: {ms * 1e3:.1f} us, {gbs:.0f} GB/s")
-    out["hop_formats_same_input"] = fmt
+    out["hop_formats_chained"] = hop_formats(ctx, whmc, torch, stream, Vh)
 
     # CG to 1e-10: FP64 vs mixed precision (32^3 x 64, kappa = 0.1575)
     b = ctx.pack_spinor(torch.from_numpy(synth.gaussian_spinor(Vh, 3003)).to(ctx.device), 0)
+    golden = load_golden(np)
     cgr = {}
-    # reference solution: FP64 CG to a true residual of 1e-13
+    # GPU reference solution: FP64 CG to a true residual of 1e-13
     ref, st = ctx.cg_solve(b, [KAPPA], whmc.cg_params(tol=1e-13))
     ref = ref.clone()
+    if golden is not None:
+        cgr["fp64_1e-13_vs_oracle"] = err_vs_golden(ctx, ref, golden, np)
     t = {}
     for name, prm in [("fp64", whmc.cg_params(tol=1e-10)),
                       ("fp64_l12", whmc.cg_params(tol=1e-10, links=whmc.L12)),
@@ -217,10 +214,17 @@ def extras(ctx, whmc, torch, np, stream, Vh):
         t[name] = ms
         cgr[name] = {"ms": round(ms, 2), "iters": s["iters"], "reliable_updates": s["reliable_updates"],
                      "true_residual": s["true_residual"], "rel_err_vs_fp64_solution": err}
-        log(f"[bench] CG {name}: {ms:.1f} ms, {s['iters']} iters, res {s['true_residual']:.2e}, err {err:.2e}")
+        if golden is not None:
+            cgr[name]["rel_err_vs_oracle"] = err_vs_golden(ctx, x, golden, np)["rel_err_sampled"]
+        log(f"[bench] CG {name}: {ms:.1f} ms, {s['iters']} iters, res {s['true_residual']:.2e}, err {err:.2e}, "
+            f"vs oracle {cgr[name].get('rel_err_vs_oracle')}")
     for name in ("fp64_l12", "mixed_f32_l12", "mixed_f16_l12"):
         cgr[name]["speedup_vs_fp64"] = round(t["fp64"] / t[name], 3)
+    if golden is not None:
+        cgr["oracle_solution"] = {"file": "tests/golden/cg_32x64_kappa0.1575.npz", "sites": int(len(golden["sites"])),
+                                  "tol": golden["meta"]["cg_tol"], "iterations": golden["meta"]["iterations"]}
     out["cg_32x64_kappa0.1575"] = cgr
+    out["cg_16x32_fp64"] = cg_16x32(whmc, torch)
 
     # M_oo x = b to |b - M_oo x| / |b| <= 1e-10: BiCGstab on M_oo (the paper's solver) against CG on
     # the normal equations M_oo^dag M_oo x = M_oo^dag b (both FP64, 18-real links; 4 hops per
@@ -240,6 +244,89 @@ def extras(ctx, whmc, torch, np, stream, Vh):
     out["force_kappa4_nt15_ms"] = round(ms, 1)
     log(f"[bench] filtered force (kappa^4, n_t=15): {ms:.1f} ms")
     return out
+
+
+def chained_pair_us(ctx, torch, stream, prec, links, x_odd, steps=20, warmup=5):
+    """microseconds per hop of the chained even/odd pair t_e = H_eo x_o, x_o' = H_oe t_e in one storage
+    format: every hop reads the previous hop's output from HBM, as in the timed region"""
+    xs = [x_odd, torch.empty_like(x_odd)]
+    te = torch.empty_like(x_odd)
+
+    def step(k):
+        ctx.apply_H(xs[k & 1], 0, prec=prec, links=links, out=te)
+        ctx.apply_H(te, 1, prec=prec, links=links, out=xs[(k + 1) & 1])
+    for k in range(warmup):
+        step(k)
+    n = [warmup]
+
+    def run():
+        for k in range(steps):
+            step(n[0] + k)
+    ms = time_events(run, stream, torch)
+    return ms * 1e3 / (2 * steps)
+
+
+def hop_formats(ctx, whmc, torch, stream, Vh):
+    """every spinor / link storage format on the chained even/odd pair of the timed region: the
+    input of each hop is the previous hop's output, resident in HBM (at 32^3 x 64 the FP64 fields
+    are 201 MB, the link arrays 0.2 - 1.2 GB); algorithmic bytes of the format per output site"""
+    from paper_1805_03560_amd import synth
+    fmt = {}
+    x64 = ctx.pack_spinor(torch.from_numpy(synth.gaussian_spinor(Vh, 3002)).to(ctx.device), 1)
+    for (p, pn), links in [((whmc.F64, "f64"), 18), ((whmc.F64, "f64"), 12), ((whmc.F32, "f32"), 18),
+                           ((whmc.F32, "f32"), 12), ((whmc.F16, "f16"), 12)]:
+        xin = x64.clone() if p == whmc.F64 else ctx.convert_spinor(x64, whmc.F64, p)
+        us = chained_pair_us(ctx, torch, stream, p, links, xin)
+        gbs = BYTES_PER_SITE[(pn, links)] * Vh / (us * 1e-6) / 1e9
+        fmt[f"{pn}_l{links}"] = {"us_per_hop": round(us, 1), "bytes_per_site": BYTES_PER_SITE[(pn, links)],
+                                 "GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 3)}
+        log(f"[bench] chained hop {pn}-{links}: {us:.1f} us, {gbs:.0f} GB/s")
+    return fmt
+
+
+def load_golden(np):
+    """the oracle's solution of the 32^3 x 64 system at sampled sites, written by
+    tests/golden/make_cg_32x64.py (oracle only); None if it is not there"""
+    base = os.path.join(ROOT, "tests", "golden", "cg_32x64_kappa0.1575")
+    if not (os.path.exists(base + ".npz") and os.path.exists(base + ".json")):
+        return None
+    z = np.load(base + ".npz", allow_pickle=False)
+    return {"sites": z["sites"], "x": z["x"], "meta": json.load(open(base + ".json"))}
+
+
+def err_vs_golden(ctx, x, golden, np):
+    import torch
+    sites = torch.from_numpy(golden["sites"]).to(ctx.device)
+    got = ctx.unpack_spinor(x, 0).index_select(0, sites).cpu().numpy()
+    ref = golden["x"]
+    return {"rel_err_sampled": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            "max_abs_err_over_max_abs": float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))}
+
+
+def cg_16x32(whmc, torch):
+    """the plain single-RHS baseline: even/odd FP64 CG to a true residual of 1e-10 on 16^3 x 32
+    smooth links (width 0.3, seed 2000), one Gaussian source (seed 2001), kappa = 0.156 and 0.1575
+    (both fields fit the 256 MB Infinity Cache)"""
+    from paper_1805_03560_amd import synth
+    dims = (32, 16, 16, 16)
+    U = synth.smooth_links(dims, 2000)
+    ctx = whmc.Context(dims, device=0)
+    ctx.load_gauge(torch.from_numpy(U).to(ctx.device), unitarity_tol=1e-11)
+    b = ctx.pack_spinor(torch.from_numpy(synth.gaussian_spinor(ctx.Vh, 2001)).to(ctx.device), 0)
+    res = {}
+    for kappa in (0.156, 0.1575):
+        prm = whmc.cg_params(tol=1e-10)
+        ctx.cg_solve(b, [kappa], prm)
+        holder = {}
+
+        def run():
+            holder["st"] = ctx.cg_solve(b, [kappa], prm)[1][0]
+        ms = time_events(run, ctx.stream, torch)
+        s = holder["st"]
+        res[f"kappa{kappa}"] = {"ms": round(ms, 2), "iters": s["iters"], "true_residual": s["true_residual"]}
+    log(f"[bench] CG 16^3x32 FP64: {res}")
+    ctx.close()
+    return res
 
 
 def bicgstab_vs_cgne(whmc, torch):
@@ -285,12 +372,12 @@ def multi_rhs(whmc, torch, stream):
         # batched hop per format (autotuned blocking: rhs per thread x lanes per site)
         for pn, p, links, lb, sb in [("f64", whmc.F64, whmc.L18, 1152, 384), ("f32_l12", whmc.F32, whmc.L12, 384, 192),
                                      ("f16_l12", whmc.F16, whmc.L12, 192, 104)]:
-            nb, lanes, _ = ctx.autotune(p, links, nrhs)
+            nb, lanes, order, _ = ctx.autotune(p, links, nrhs)
             bp = b if p == whmc.F64 else ctx.convert_spinor(b, whmc.F64, p, nrhs)
             o = ctx.half_spinor(p, nrhs)
             ms = time_events(lambda: ctx.apply_H_multi(bp, 0, nrhs, prec=p, links=links, out=o, rhs_block=nb,
-                                                       rhs_lanes=lanes), stream, torch, reps=10)
-            row[f"hop_{pn}_blocking"] = [nb, lanes]
+                                                       rhs_lanes=lanes, rhs_order=order), stream, torch, reps=10)
+            row[f"hop_{pn}_blocking"] = [nb, lanes, order]
             row[f"hop_{pn}_us_per_rhs"] = round(ms * 1e3 / nrhs, 2)
             row[f"hop_{pn}_GBps"] = round(Vh * (lb + sb * nrhs) / (ms * 1e-3) / 1e9, 1)
         # CG to 1e-10: sequential FP64, masked multi-RHS FP64, masked multi-RHS mixed FP32-12
@@ -439,7 +526,10 @@ def widened_16x32(whmc, torch):
     t0 = time.perf_counter()
     tr = ctx.rooted_trajectory(p, pi0, eta, 0.5)
     res["trajectory"] = {"seconds": round(time.perf_counter() - t0, 3), "dH": tr["dH"], "cg_iters": tr["cg_iters"],
-                         "n_solves": tr["n_solves"], "poly_iters": tr["poly_iters"]}
+                         "n_solves": tr["n_solves"], "poly_iters": tr["poly_iters"],
+                         "note": "timing of one trajectory's kernels; the synthetic field is far from equilibrium of "
+                                 "the beta = 5.6 rooted action, so |dH| is large (on thermalised fields the same "
+                                 "settings give P_acc = 0.77, see the ensemble runs)"}
     out["rooted_16x32_kappa0.1575"] = res
     log(f"[bench] rooted N=4 (8,32) 16^3x32: {res}")
 
@@ -464,13 +554,30 @@ def widened_16x32(whmc, torch):
     return out
 
 
-def cpu_baseline():
-    """the FP64 numpy oracle's even/odd hop, timed on this host on a bounded sample: H_eo on the
-    16^3 x 32 lattice (the oracle's numpy kernels run on one thread)."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(gpu_iters_16x32=None):
+    """The FP64 numpy oracle as it stands, timed on this host on bounded samples (its numpy kernels
+    run on one thread):
+    - H_eo on 16^3 x 32 -- the oracle forms the even/odd block by applying the full-lattice H to a
+      field that is zero on the other parity, twice the arithmetic of an even/odd hop; `value` is
+      the even/odd hop's algorithmic bytes (1536 B per output site) per second of that;
+    - its even/odd CG to a residual of 1e-10 on 4^4 (Haar links, seed 1000, kappa = 0.156), whole;
+    - M_oo^dag M_oo on 16^3 x 32 (one CG iteration's operator), times the iteration count of the
+      GPU's 16^3 x 32 solve at kappa = 0.156: an extrapolated oracle CG time, labelled as such."""
     import numpy as np
 
     from oracle import dirac
     from oracle.lattice import Lattice
+    from oracle.solve import cg
     from paper_1805_03560_amd import synth
     dims = (32, 16, 16, 16)
     lat = Lattice(dims)
@@ -479,15 +586,36 @@ def cpu_baseline():
     dirac.apply_Hblock(lat, U, x, 0)
     reps, t = 0, 0.0
     t0 = time.perf_counter()
-    while t < 10.0 and reps < 50:
+    while t < 8.0 and reps < 50:
         dirac.apply_Hblock(lat, U, x, 0)
         reps += 1
         t = time.perf_counter() - t0
     gbs = 1536 * lat.Vh * reps / t / 1e9
     log(f"[bench] oracle H_eo 16^3x32: {t / reps:.2f} s/hop, {gbs:.3f} GB/s")
+    # whole CG on 4^4
+    d4 = (4, 4, 4, 4)
+    l4 = Lattice(d4)
+    U4 = synth.haar_links(d4, 1000)
+    b4 = synth.gaussian_spinor(l4.Vh, 0)
+    t0 = time.perf_counter()
+    _, it4, res4 = cg(lambda v: dirac.apply_MooDagMoo(l4, U4, v, 0.156), b4, tol=1e-10)
+    t4 = time.perf_counter() - t0
+    # operator of one CG iteration on 16^3 x 32
+    t0 = time.perf_counter()
+    for _ in range(2):
+        dirac.apply_MooDagMoo(lat, U, x, 0.156)
+    t_op = (time.perf_counter() - t0) / 2
+    cg16 = {"seconds_per_iteration": round(t_op, 3)}
+    if gpu_iters_16x32:
+        cg16["iterations_of_the_gpu_solve"] = gpu_iters_16x32
+        cg16["extrapolated_seconds"] = round(t_op * gpu_iters_16x32, 1)
+    log(f"[bench] oracle CG 4^4: {it4} iters in {t4:.2f} s; 16^3x32 M^dag M: {t_op:.2f} s")
     return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} oracle H_eo applications on 16^3x32 (Vh={lat.Vh}), {t / reps:.2f} s each; "
-                      f"host {platform.processor() or platform.machine()}, os.cpu_count()={os.cpu_count()}"}
+            "sample": f"{reps} oracle H_eo applications on 16^3x32 (Vh={lat.Vh}, computed as a full-lattice H on "
+                      f"a half-zero field), {t / reps:.2f} s each, one thread",
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
+            "cg_4x4_kappa0.156_to_1e-10": {"seconds": round(t4, 3), "iterations": it4, "true_residual": res4},
+            "cg_16x32_kappa0.156_to_1e-10_extrapolated": cg16}
 
 
 if __name__ == "__main__":

@@ -62,7 +62,12 @@ typedef enum whmc_status {
 } whmc_status;
 
 typedef enum whmc_prec { WHMC_F64 = 0, WHMC_F32 = 1, WHMC_F16 = 2 } whmc_prec;
-typedef enum whmc_links { WHMC_L12 = 12, WHMC_L18 = 18 } whmc_links;
+/* link storage: 18 reals (all entries), 12 (rows 0 and 1; row 2 = conj(row 0 x row 1)) or 8 (U01, U02,
+ * one of U10 / U20 and two phases; the 8-parameter form of Clark et al., Comput. Phys. Commun. 181
+ * (2010) 1517).  The 8-real form needs |U01|^2 + |U02|^2 > 0 on every link (> 1e-20 in FP64 and
+ * FP32, > 1e-6 in FP16); a field with a link that violates it gives WHMC_EUNSUP when the format is
+ * first used (e.g. unit links). */
+typedef enum whmc_links { WHMC_L8 = 8, WHMC_L12 = 12, WHMC_L18 = 18 } whmc_links;
 typedef enum whmc_integrator { WHMC_LEAPFROG = 0, WHMC_OMELYAN = 1 } whmc_integrator;
 
 typedef struct whmc_ctx whmc_ctx;
@@ -88,8 +93,29 @@ whmc_status whmc_set_stream(whmc_ctx* ctx, void* stream);
  *                              longer fits the caches; smaller lattices run faster without it).
  * EARG for an unknown option or a value below -1. */
 #define WHMC_OPT_STREAM_THRESHOLD 1
+/*   WHMC_OPT_HOP_SCHEDULE      order of the workgroups of the single-RHS stencil, solver and
+ *                              BiCGstab kernels: 0 = each XCD takes one eighth of every time slice
+ *                              and sweeps t (default); 1 = each XCD takes L_t / 8 consecutive time
+ *                              slices and works through them in chunks of WHMC_OPT_HOP_CHUNK blocks
+ *                              of 128 sites of a slice (needs L_t divisible by 8 and time slices of
+ *                              whole blocks, else EARG).  Results do not depend on it.
+ *   WHMC_OPT_HOP_CHUNK         chunk of schedule 1, 1 .. blocks per time slice.
+ *   WHMC_OPT_FORCE_KERNEL      pseudo-fermion force contraction: 0 = one thread per link (default),
+ *                              1 = one thread per site and its four links.
+ *   WHMC_OPT_FORCE_CHUNK       (X, Y) pairs summed per launch of that contraction, 1 .. 24 (default
+ *                              24); later launches accumulate.  Results agree to rounding. */
+#define WHMC_OPT_HOP_SCHEDULE 2
+#define WHMC_OPT_HOP_CHUNK 3
+#define WHMC_OPT_FORCE_KERNEL 4
+#define WHMC_OPT_FORCE_CHUNK 5
 whmc_status whmc_set_option(whmc_ctx* ctx, int option, long long value);
 whmc_status whmc_get_option(const whmc_ctx* ctx, int option, long long* value);
+
+/* Autotuner of the single-RHS stencil schedule: times the FP64 even/odd hop pair (H_eo then H_oe,
+ * 18-real links) for schedule 0 and for schedule 1 with chunks of 1/16 .. 1/2 of a time slice, and
+ * keeps the fastest in the context (WHMC_OPT_HOP_SCHEDULE / WHMC_OPT_HOP_CHUNK).  Outputs may be
+ * NULL; us receives the time per hop in microseconds.  Uses context scratch of two half fields. */
+whmc_status whmc_autotune_hop(whmc_ctx* ctx, int* schedule, int* chunk, double* us);
 
 /* Bytes of one field of the given kind in the whmc layout:
  * kind 0 = half spinor, 1 = full spinor, 2 = algebra field (prec ignored), 3 = canonical gauge. */
@@ -118,27 +144,34 @@ whmc_status whmc_unpack_algebra(whmc_ctx* ctx, double* dst, const double* src);
  * out_parity p in {0, 1}: out (half field of parity p) = H_{p,1-p} in (half field of parity 1-p),
  * i.e. H_eo for p = 0 and H_oe for p = 1; dagger = 1 applies the same block of H^dag.
  * out_parity = -1: out (full) = H in (full), computed as both blocks.
- * prec selects the spinor format of in/out, links the link format (F64 supports L18 and L12;
- * F32 supports L18 and L12; F16 supports L12).  in and out must not overlap. */
+ * prec selects the spinor format of in/out, links the link format (F64 and F32 support L18, L12
+ * and L8; F16 supports L12 and L8).  in and out must not overlap. */
 whmc_status whmc_apply_H(whmc_ctx* ctx, void* out, const void* in, int out_parity, int dagger, int prec, int links);
 
 /* Multi right-hand-side form of the even/odd hop: out_r = H_{p,1-p} in_r for r < nrhs (nrhs
  * consecutive half fields in and out, 1 <= nrhs <= 16).  Blocking: each thread applies the links
  * of its site to rhs_block right-hand sides held in registers (one link load and decode serves
  * them all), and rhs_lanes lanes of a wavefront hold the same site for further right-hand sides,
- * sharing each link load instruction; the groups of right-hand sides of a site block run back to
- * back on one XCD so the links are reused from its L2.  Allowed: FP64 (18- or 12-real links)
- * rhs_block = 1 with rhs_lanes = 1, 2 or 4; FP32 / FP16 (12-real links) rhs_block = 1, 2 or 4
- * with rhs_lanes = 1 or 2.  rhs_block = rhs_lanes = 0 takes the autotuned blocking; one of them 0
- * reads as 1; anything else is WHMC_EARG. */
+ * sharing each link load instruction.  The right-hand sides thus form groups of
+ * rhs_block * rhs_lanes; rhs_order chooses the order of the workgroups:
+ *   0 (block-major): the groups of a site block run back to back on one XCD, so the links are
+ *     reused from its L2 (each link read from memory once per call);
+ *   1 (group-major): each group sweeps the whole lattice before the next, so the neighbour
+ *     spinors of the group stay in L2 (the links are read once per group).
+ * Allowed: FP64 (18- or 12-real links) rhs_block = 1 with rhs_lanes = 1, 2 or 4, or rhs_block = 2 with
+ * rhs_lanes = 1 or 2; FP32 / FP16
+ * (12-real links) rhs_block = 1, 2 or 4 with rhs_lanes = 1 or 2.  rhs_block = rhs_lanes = 0
+ * takes the autotuned blocking and order (rhs_order ignored); one of them 0 reads as 1; anything
+ * else is WHMC_EARG. */
 whmc_status whmc_apply_H_multi(whmc_ctx* ctx, void* out, const void* in, int out_parity, int dagger, int prec,
-                               int links, int nrhs, int rhs_block, int rhs_lanes);
+                               int links, int nrhs, int rhs_block, int rhs_lanes, int rhs_order);
 
-/* Autotuner: time the multi-RHS hop for every allowed blocking not wider than needed for nrhs
- * at this lattice size, precision and link format, remember the fastest in the context and
- * return it (and its time per launch in microseconds if us != NULL).  Later calls with the same
- * key return the stored choice without timing. */
-whmc_status whmc_autotune(whmc_ctx* ctx, int prec, int links, int nrhs, int* rhs_block, int* rhs_lanes, double* us);
+/* Autotuner: time the multi-RHS hop for every allowed blocking and order not wider than needed
+ * for nrhs at this lattice size, precision and link format, remember the fastest in the context
+ * and return it (rhs_order may be NULL; us, if not NULL, receives its time per launch in
+ * microseconds).  Later calls with the same key return the stored choice without timing. */
+whmc_status whmc_autotune(whmc_ctx* ctx, int prec, int links, int nrhs, int* rhs_block, int* rhs_lanes,
+                          int* rhs_order, double* us);
 
 /* out = M_oo in = in - kappa^2 H_oe H_eo in (dagger = 0) or M_oo^dag in (dagger = 1), FP64,
  * odd-site half fields (Sec. 2.2).  Uses context scratch for the even-site intermediate. */
@@ -178,6 +211,7 @@ typedef struct whmc_cg_params {
   int check_every;    /* iterations enqueued between host convergence checks (>= 1) */
   int rhs_block;      /* multi-RHS register block (right-hand sides per thread), 0 = autotuned */
   int rhs_lanes;      /* multi-RHS lanes per site sharing link loads, 0 = autotuned */
+  int rhs_order;      /* multi-RHS workgroup order (see whmc_apply_H_multi); ignored when autotuned */
 } whmc_cg_params;
 
 typedef struct whmc_cg_stats {

@@ -245,10 +245,11 @@ __global__ void k_bs_init(BSScalars* sc, const double* rr0, double stop_rr) {
 template <int DAG, class Lnk>
 static void enqueue_bs(whmc_ctx* c, const Lnk& L, SpinorF64 x, SpinorF64 r, SpinorF64 rhat, SpinorF64 p,
                        SpinorF64 v, SpinorF64 s, SpinorF64 t, SpinorF64 te, double k2, BSScalars* sc, int n) {
-  const int ns = c->stencil_blocks(), nv = c->num_blocks();
+  const int ns = c->site_blocks(), nv = c->num_blocks();
   const dim3 gs(ns), gv(nv), blk(kBlock);
   const Reduce red = c->red;
   for (int it = 0; it < n; ++it) {
+    TraceRange tr("whmc bicgstab iteration");
     hipLaunchKernelGGL((k_bs_hop<DAG, Lnk>), gs, blk, 0, c->stream, c->g, L, p, te, sc);
     hipLaunchKernelGGL((k_bs_mv<DAG, 0, Lnk>), gs, blk, 0, c->stream, c->g, L, te, p, v, rhat, k2, sc, red, ns);
     hipLaunchKernelGGL(k_bs_fin<0>, dim3(1), dim3(256), 0, c->stream, sc, red.partials, ns);

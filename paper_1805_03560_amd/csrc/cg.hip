@@ -274,9 +274,10 @@ static SpinorF16 s16(void* p, int Vh) { return SpinorF16{(uint4*)p, (float*)((ui
 
 template <class Lnk, class S, class SR, bool MIXED>
 static whmc_status enqueue_iters(whmc_ctx* c, const Lnk& L, S p, S t, S u, S v, SR r, SR x, double kappa, int n) {
-  const dim3 grid(c->stencil_blocks()), block(kBlock);
+  const dim3 grid(c->site_blocks()), block(kBlock);
   const double k2 = kappa * kappa;
   for (int it = 0; it < n; ++it) {
+    TraceRange tr(MIXED ? "whmc cg iteration (mixed)" : "whmc cg iteration");
     hipLaunchKernelGGL((k_cg1<Lnk, S>), grid, block, 0, c->stream, c->g, L, p, t, c->scal);
     hipLaunchKernelGGL((k_cg2<Lnk, S>), grid, block, 0, c->stream, c->g, L, t, p, u, k2, c->scal, c->red);
     hipLaunchKernelGGL(k_cg2_fin, dim3(1), dim3(256), 0, c->stream, c->scal, c->red.partials, (int)grid.x);
@@ -405,7 +406,7 @@ static whmc_status cg_mixed(whmc_ctx* c, double* x, const double* b, double kapp
                      prm->tol * prm->tol, prm->delta * prm->delta);
   WHMC_HIP(hipGetLastError());
   const int check = prm->check_every > 0 ? prm->check_every : 8;
-  const dim3 grid(c->stencil_blocks()), block(kBlock);
+  const dim3 grid(c->site_blocks()), block(kBlock);
   CGScalars hs{};
   int iters = 0;
   double rel = 1.0;
@@ -457,6 +458,7 @@ whmc_status cg_solve_multi(whmc_ctx* c, double* x, const double* b, const double
 whmc_status cg_solve(whmc_ctx* c, double* x, const double* b, const double* kappas, int nrhs,
                      const whmc_cg_params* p, whmc_cg_stats* st) {
   WHMC_CHECK(c->gauge_loaded, WHMC_ESTATE, "no gauge field loaded");
+  TraceRange tr(nrhs > 1 ? "whmc cg solve (multi-rhs)" : "whmc cg solve");
   if (nrhs > 1) return cg_solve_multi(c, x, b, kappas, nrhs, p, st);
   whmc_cg_stats local{};
   whmc_cg_stats* s = st ? st : &local;
@@ -467,6 +469,10 @@ whmc_status cg_solve(whmc_ctx* c, double* x, const double* b, const double* kapp
     WHMC_TRY(ensure_links(c, WHMC_F64, WHMC_L12));
     if (c->stream_links(WHMC_F64, WHMC_L12)) rc = cg_f64(c, x, b, kappas[0], p, s, LinkF64_12T<true>{c->U12, Vh});
     else rc = cg_f64(c, x, b, kappas[0], p, s, LinkF64_12T<false>{c->U12, Vh});
+  } else if (p->prec == WHMC_F64 && p->links == WHMC_L8) {
+    WHMC_TRY(ensure_links(c, WHMC_F64, WHMC_L8));
+    if (c->stream_links(WHMC_F64, WHMC_L8)) rc = cg_f64(c, x, b, kappas[0], p, s, LinkF64_8T<true>{c->U8, Vh});
+    else rc = cg_f64(c, x, b, kappas[0], p, s, LinkF64_8T<false>{c->U8, Vh});
   } else if (p->prec == WHMC_F64) {
     if (c->stream_links(WHMC_F64, WHMC_L18)) rc = cg_f64(c, x, b, kappas[0], p, s, LinkF64_18T<true>{c->U18, Vh});
     else rc = cg_f64(c, x, b, kappas[0], p, s, LinkF64_18T<false>{c->U18, Vh});
@@ -476,17 +482,25 @@ whmc_status cg_solve(whmc_ctx* c, double* x, const double* b, const double* kapp
     if (p->links == WHMC_L18) {
       if (nt) rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF32_18T<true>{c->U32_18, Vh}, WHMC_F32, s32, s32, WHMC_F32);
       else rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF32_18T<false>{c->U32_18, Vh}, WHMC_F32, s32, s32, WHMC_F32);
+    } else if (p->links == WHMC_L8) {
+      if (nt) rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF32_8T<true>{c->U32_8, Vh}, WHMC_F32, s32, s32, WHMC_F32);
+      else rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF32_8T<false>{c->U32_8, Vh}, WHMC_F32, s32, s32, WHMC_F32);
     } else {
       if (nt) rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF32_12T<true>{c->U32_12, Vh}, WHMC_F32, s32, s32, WHMC_F32);
       else rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF32_12T<false>{c->U32_12, Vh}, WHMC_F32, s32, s32, WHMC_F32);
     }
   } else {
-    WHMC_CHECK(p->links == WHMC_L12, WHMC_EUNSUP, "FP16 bulk requires 12-real links");
-    WHMC_TRY(ensure_links(c, WHMC_F16, WHMC_L12));
-    if (c->stream_links(WHMC_F16, WHMC_L12))
+    WHMC_CHECK(p->links == WHMC_L12 || p->links == WHMC_L8, WHMC_EUNSUP, "FP16 bulk requires 12- or 8-real links");
+    WHMC_TRY(ensure_links(c, WHMC_F16, p->links));
+    const bool nt = c->stream_links(WHMC_F16, p->links);
+    if (p->links == WHMC_L8) {
+      if (nt) rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF16_8T<true>{c->U16_8, Vh}, WHMC_F16, s16, s32, WHMC_F32);
+      else rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF16_8T<false>{c->U16_8, Vh}, WHMC_F16, s16, s32, WHMC_F32);
+    } else if (nt) {
       rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF16_12T<true>{c->U16_12, Vh}, WHMC_F16, s16, s32, WHMC_F32);
-    else
+    } else {
       rc = cg_mixed(c, x, b, kappas[0], p, s, LinkF16_12T<false>{c->U16_12, Vh}, WHMC_F16, s16, s32, WHMC_F32);
+    }
   }
   if (rc != WHMC_OK) return rc;
   if (!s->converged) {

@@ -12,6 +12,7 @@ namespace whmc {
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+
 whmc_status workspace(whmc_ctx* c, const std::string& name, size_t bytes, void** out) {
   auto it = c->ws.find(name);
   if (it != c->ws.end() && it->second.second >= bytes) {
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_hop(Geom g, int par, Lnk L, SIn in, 
 template <class Lnk, class S>
 static whmc_status launch_hop(whmc_ctx* c, const Lnk& L, int par, int dag, S in, S x, S out, bool xpay, double a,
                               double b, double* norm_out, bool nts) {
-  dim3 grid(c->stencil_blocks()), block(kBlock);
+  dim3 grid(c->site_blocks()), block(kBlock);
 #define WHMC_L(D, XP, N, NS) hipLaunchKernelGGL((k_hop<D, XP, N, NS, Lnk, S, S, S>), grid, block, 0, c->stream, c->g, \
                                                 par, L, in, x, out, a, b, c->red, norm_out)
   const bool norm = norm_out != nullptr;
@@ -94,6 +95,9 @@ static whmc_status hop_nt(whmc_ctx* c, int prec, int links, int par, int dag, vo
     if (links == WHMC_L18)
       return launch_hop(c, LinkF64_18T<NT>{c->U18, Vh}, par, dag, sp64(in, Vh), sp64(x, Vh), sp64(out, Vh), xpay, a,
                         b, norm_out, nts);
+    if (links == WHMC_L8)
+      return launch_hop(c, LinkF64_8T<NT>{c->U8, Vh}, par, dag, sp64(in, Vh), sp64(x, Vh), sp64(out, Vh), xpay, a, b,
+                        norm_out, nts);
     return launch_hop(c, LinkF64_12T<NT>{c->U12, Vh}, par, dag, sp64(in, Vh), sp64(x, Vh), sp64(out, Vh), xpay, a, b,
                       norm_out, nts);
   }
@@ -101,9 +105,15 @@ static whmc_status hop_nt(whmc_ctx* c, int prec, int links, int par, int dag, vo
     if (links == WHMC_L18)
       return launch_hop(c, LinkF32_18T<NT>{c->U32_18, Vh}, par, dag, sp32(in, Vh), sp32(x, Vh), sp32(out, Vh), xpay,
                         a, b, norm_out, nts);
+    if (links == WHMC_L8)
+      return launch_hop(c, LinkF32_8T<NT>{c->U32_8, Vh}, par, dag, sp32(in, Vh), sp32(x, Vh), sp32(out, Vh), xpay, a,
+                        b, norm_out, nts);
     return launch_hop(c, LinkF32_12T<NT>{c->U32_12, Vh}, par, dag, sp32(in, Vh), sp32(x, Vh), sp32(out, Vh), xpay, a,
                       b, norm_out, nts);
   }
+  if (links == WHMC_L8)
+    return launch_hop(c, LinkF16_8T<NT>{c->U16_8, Vh}, par, dag, sp16(in, Vh), sp16(x, Vh), sp16(out, Vh), xpay, a, b,
+                      norm_out, nts);
   return launch_hop(c, LinkF16_12T<NT>{c->U16_12, Vh}, par, dag, sp16(in, Vh), sp16(x, Vh), sp16(out, Vh), xpay, a,
                     b, norm_out, nts);
 }
@@ -146,20 +156,23 @@ static whmc_status hop_full_nt(whmc_ctx* c, int prec, int links, int dag, void* 
   if (prec == WHMC_F64) {
     auto ie = sp64(i0, Vh), io = sp64(i0 + hb, Vh), oe = sp64(o0, Vh), oo = sp64(o0 + hb, Vh);
     if (links == WHMC_L18) return launch_full(c, LinkF64_18T<NT>{c->U18, Vh}, dag, ie, io, oe, oo, nts);
+    if (links == WHMC_L8) return launch_full(c, LinkF64_8T<NT>{c->U8, Vh}, dag, ie, io, oe, oo, nts);
     return launch_full(c, LinkF64_12T<NT>{c->U12, Vh}, dag, ie, io, oe, oo, nts);
   }
   if (prec == WHMC_F32) {
     auto ie = sp32(i0, Vh), io = sp32(i0 + hb, Vh), oe = sp32(o0, Vh), oo = sp32(o0 + hb, Vh);
     if (links == WHMC_L18) return launch_full(c, LinkF32_18T<NT>{c->U32_18, Vh}, dag, ie, io, oe, oo, nts);
+    if (links == WHMC_L8) return launch_full(c, LinkF32_8T<NT>{c->U32_8, Vh}, dag, ie, io, oe, oo, nts);
     return launch_full(c, LinkF32_12T<NT>{c->U32_12, Vh}, dag, ie, io, oe, oo, nts);
   }
   auto ie = sp16(i0, Vh), io = sp16(i0 + hb, Vh), oe = sp16(o0, Vh), oo = sp16(o0 + hb, Vh);
+  if (links == WHMC_L8) return launch_full(c, LinkF16_8T<NT>{c->U16_8, Vh}, dag, ie, io, oe, oo, nts);
   return launch_full(c, LinkF16_12T<NT>{c->U16_12, Vh}, dag, ie, io, oe, oo, nts);
 }
 
 whmc_status hop_full(whmc_ctx* c, int prec, int links, int dag, void* out, const void* in) {
   WHMC_TRY(ensure_links(c, prec, links));
-  if (prec == WHMC_F16 && links != WHMC_L12) {
+  if (prec == WHMC_F16 && links == WHMC_L18) {
     set_error("unsupported precision / link format combination");
     return WHMC_EUNSUP;
   }
@@ -220,20 +233,50 @@ __global__ void k_unitarity(int n, const double2* __restrict__ U18, int Vh, unsi
                        cmul(U.e[0][2], cmul(U.e[1][0], U.e[2][1]) - cmul(U.e[1][1], U.e[2][0]));
     det.re -= 1.0;
     dev = fmax(dev, sqrt(norm2(det)));
-    if (!(dev == dev)) dev = 1e300;  // NaN counts as failure
+    // fmax drops NaN operands, so a non-finite entry is checked for explicitly and counts as failure
+    bool finite = true;
+    for (int k = 0; k < 9; ++k) finite = finite && isfinite(U.e[k / 3][k % 3].re) && isfinite(U.e[k / 3][k % 3].im);
+    if (!finite) dev = 1e300;
   }
   for (int off = 32; off > 0; off >>= 1) dev = fmax(dev, __shfl_xor(dev, off, 64));
   if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(dev));
 }
 
-// derived link formats from the FP64 18-real master, one thread per (parity, mu, cb)
-__global__ void k_derive_links(int n, int Vh, const double2* __restrict__ U18, int fmt, void* dst) {
+// derived link formats from the FP64 18-real master, one thread per (parity, mu, cb); the 8-real
+// formats also report min over links of n = |U01|^2 + |U02|^2 (ordered bits of a double >= 0)
+__global__ void k_derive_links(int n, int Vh, const double2* __restrict__ U18, int fmt, void* dst,
+                               unsigned long long* nmin) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n) return;
+  double nn = 1.0;
+  if (idx < n) {
   const int pm = idx / Vh, i = idx - pm * Vh;
   double2 v[9];
   for (int k = 0; k < 9; ++k) v[k] = U18[(size_t)pm * 9 * Vh + aos(k, i, 9, Vh)];
-  if (fmt == 0) {  // F64-12
+  if (fmt >= 4) {  // 8-real: U01, U02, the smaller of U10 / U20, phases (see reconstruct8)
+    nn = v[1].x * v[1].x + v[1].y * v[1].y + v[2].x * v[2].x + v[2].y * v[2].y;
+    const double t00 = atan2(v[0].y, v[0].x);
+    const bool swap = fmt != 6 && (v[6].x * v[6].x + v[6].y * v[6].y < v[3].x * v[3].x + v[3].y * v[3].y);
+    const double2 s = swap ? v[6] : v[3];
+    const double ts = swap ? atan2(v[3].y, v[3].x) + 8.0 : atan2(v[6].y, v[6].x);
+    if (fmt == 4) {
+      double2* d = (double2*)dst + (size_t)pm * 4 * Vh;
+      d[aos(0, i, 4, Vh)] = v[1];
+      d[aos(1, i, 4, Vh)] = v[2];
+      d[aos(2, i, 4, Vh)] = s;
+      d[aos(3, i, 4, Vh)] = make_double2(t00, ts);
+    } else if (fmt == 5) {
+      float4* d = (float4*)dst + (size_t)pm * 2 * Vh;
+      d[aos(0, i, 2, Vh)] = make_float4((float)v[1].x, (float)v[1].y, (float)v[2].x, (float)v[2].y);
+      d[aos(1, i, 2, Vh)] = make_float4((float)s.x, (float)s.y, (float)t00, (float)ts);
+    } else {
+      const double ipi = 0.31830988618379067;
+      uint4* d = (uint4*)dst + (size_t)pm * Vh;
+      d[aos(0, i, 1, Vh)] = make_uint4((unsigned)f2h((float)v[1].x) | ((unsigned)f2h((float)v[1].y) << 16),
+                                       (unsigned)f2h((float)v[2].x) | ((unsigned)f2h((float)v[2].y) << 16),
+                                       (unsigned)f2h((float)s.x) | ((unsigned)f2h((float)s.y) << 16),
+                                       (unsigned)f2h((float)(t00 * ipi)) | ((unsigned)f2h((float)(ts * ipi)) << 16));
+    }
+  } else if (fmt == 0) {  // F64-12
     double2* d = (double2*)dst;
     for (int k = 0; k < 6; ++k) d[(size_t)pm * 6 * Vh + aos(k, i, 6, Vh)] = v[k];
   } else if (fmt == 1) {  // F32-18
@@ -252,10 +295,15 @@ __global__ void k_derive_links(int n, int Vh, const double2* __restrict__ U18, i
       d[(size_t)pm * 3 * Vh + aos(k, i, 3, Vh)] = make_uint2(w0, w1);
     }
   }
+  }
+  if (nmin) {
+    for (int off = 32; off > 0; off >>= 1) nn = fmin(nn, __shfl_xor(nn, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMin(nmin, (unsigned long long)__double_as_longlong(nn));
+  }
 }
 
 whmc_status gauge_changed(whmc_ctx* c) {
-  for (int k = 0; k < 4; ++k) c->derived_valid[k] = false;
+  for (int k = 0; k < 7; ++k) c->derived_valid[k] = false;
   return WHMC_OK;
 }
 
@@ -270,6 +318,9 @@ whmc_status ensure_links(whmc_ctx* c, int prec, int links) {
   else if (prec == WHMC_F32 && links == WHMC_L18) { fmt = 1; bytes = nl * 9 * sizeof(float2); slot = (void**)&c->U32_18; }
   else if (prec == WHMC_F32 && links == WHMC_L12) { fmt = 2; bytes = nl * 3 * sizeof(float4); slot = (void**)&c->U32_12; }
   else if (prec == WHMC_F16 && links == WHMC_L12) { fmt = 3; bytes = nl * 3 * sizeof(uint2); slot = (void**)&c->U16_12; }
+  else if (prec == WHMC_F64 && links == WHMC_L8) { fmt = 4; bytes = nl * 4 * sizeof(double2); slot = (void**)&c->U8; }
+  else if (prec == WHMC_F32 && links == WHMC_L8) { fmt = 5; bytes = nl * 2 * sizeof(float4); slot = (void**)&c->U32_8; }
+  else if (prec == WHMC_F16 && links == WHMC_L8) { fmt = 6; bytes = nl * sizeof(uint4); slot = (void**)&c->U16_8; }
   else {
     set_error("unsupported precision / link format combination");
     return WHMC_EUNSUP;
@@ -277,8 +328,29 @@ whmc_status ensure_links(whmc_ctx* c, int prec, int links) {
   if (c->derived_valid[fmt]) return WHMC_OK;
   if (*slot == nullptr) WHMC_HIP(hipMalloc(slot, bytes));
   const int n = (int)nl;
-  hipLaunchKernelGGL(k_derive_links, dim3((n + 255) / 256), dim3(256), 0, c->stream, n, c->Vh, c->U18, fmt, *slot);
+  unsigned long long* nmin = nullptr;
+  if (fmt >= 4) {
+    void* w;
+    WHMC_TRY(workspace(c, "derive_nmin", sizeof(unsigned long long), &w));
+    nmin = (unsigned long long*)w;
+    const double one = 1.0;
+    WHMC_HIP(hipMemcpyAsync(nmin, &one, sizeof(one), hipMemcpyHostToDevice, c->stream));
+  }
+  hipLaunchKernelGGL(k_derive_links, dim3((n + 255) / 256), dim3(256), 0, c->stream, n, c->Vh, c->U18, fmt, *slot,
+                     nmin);
   WHMC_HIP(hipGetLastError());
+  if (nmin) {
+    // the 8-real form needs n = |U01|^2 + |U02|^2 > 0 on every link (reconstruct8); half precision
+    // needs it well inside the normal FP16 range
+    WHMC_HIP(hipMemcpyAsync(c->host_pinned, nmin, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    WHMC_HIP(hipStreamSynchronize(c->stream));
+    const double lim = fmt == 6 ? 1e-6 : 1e-20;
+    if (!(c->host_pinned[0] >= lim)) {
+      set_error("8-real links: a link has |U01|^2 + |U02|^2 = " + std::to_string(c->host_pinned[0]) + " < " +
+                std::to_string(lim) + " (|U00| = 1 to that precision), which the 8-real form cannot represent");
+      return WHMC_EUNSUP;
+    }
+  }
   c->derived_valid[fmt] = true;
   return WHMC_OK;
 }
@@ -511,6 +583,8 @@ whmc_status whmc_create(whmc_ctx** out, const int dims[4], int device, void* str
     const bool split = slice % kBlock == 0 && slice / kBlock >= 8;
     c->g.nbs = split ? (int)(slice / kBlock) : 0;
     c->g.xq = split ? (c->g.nbs + 7) / 8 : 0;
+    c->g.sched = 0;
+    c->hop_chunk = c->g.xq;   // chunk of the time-slab schedule: one XCD's range of a slice
   }
   c->device = device;
   c->stream = (hipStream_t)stream;
@@ -544,6 +618,9 @@ void whmc_destroy(whmc_ctx* c) {
   (void)hipFree(c->U32_18);
   (void)hipFree(c->U32_12);
   (void)hipFree(c->U16_12);
+  (void)hipFree(c->U8);
+  (void)hipFree(c->U32_8);
+  (void)hipFree(c->U16_8);
   (void)hipFree(c->red.partials);
   (void)hipFree(c->red.counter);
   (void)hipFree(c->red.result);
@@ -642,7 +719,8 @@ whmc_status whmc_apply_H(whmc_ctx* c, void* out, const void* in, int out_parity,
   WHMC_CHECK(out != in, WHMC_EARG, "whmc_apply_H: in and out must differ");
   WHMC_CHECK(out_parity >= -1 && out_parity <= 1, WHMC_EARG, "whmc_apply_H: out_parity must be -1, 0 or 1");
   WHMC_CHECK(prec >= 0 && prec <= 2, WHMC_EARG, "whmc_apply_H: bad precision");
-  WHMC_CHECK(links == WHMC_L12 || links == WHMC_L18, WHMC_EARG, "whmc_apply_H: links must be 12 or 18");
+  WHMC_CHECK(links == WHMC_L8 || links == WHMC_L12 || links == WHMC_L18, WHMC_EARG,
+             "whmc_apply_H: links must be 8, 12 or 18");
   const int dag = dagger ? 1 : 0;
   if (out_parity >= 0) return hop(c, prec, links, out_parity, dag, out, in, nullptr, 0.0, 1.0, nullptr, true);
   return hop_full(c, prec, links, dag, out, in);
@@ -678,12 +756,87 @@ whmc_status whmc_apply_MdagM(whmc_ctx* c, double* out, const double* in, const d
   return WHMC_OK;
 }
 
+// Autotuner of the single-RHS stencil schedule: times the FP64 even/odd hop pair t = H_eo x,
+// x' = H_oe t (18-real links, the order of the even/odd operator) on zero fields for the slice-range
+// schedule and the time-slab schedule with chunks of nbs/16 .. nbs/2 blocks, keeps the fastest.
+whmc_status whmc_autotune_hop(whmc_ctx* c, int* schedule, int* chunk, double* us) {
+  WHMC_CHECK(c, WHMC_EARG, "whmc_autotune_hop: null context");
+  WHMC_CHECK(c->gauge_loaded, WHMC_ESTATE, "no gauge field loaded");
+  const size_t hb = (size_t)c->Vh * 192;
+  void *x, *t;
+  WHMC_TRY(workspace(c, "tune_hop_x", hb, &x));
+  WHMC_TRY(workspace(c, "tune_hop_t", hb, &t));
+  WHMC_TRY(zero_bytes(c, x, hb));
+  std::vector<std::pair<int, int>> cand{{0, c->hop_chunk}};
+  if (c->g.nbs > 0 && c->g.L[0] % 8 == 0)
+    for (int d : {16, 8, 4, 2}) {
+      const int q = (c->g.nbs + d - 1) / d;
+      bool seen = false;
+      for (auto& p : cand) seen |= (p.first == 1 && p.second == q);
+      if (!seen) cand.push_back({1, q});
+    }
+  hipEvent_t e0, e1;
+  WHMC_HIP(hipEventCreate(&e0));
+  WHMC_HIP(hipEventCreate(&e1));
+  const Geom saved = c->g;
+  double best = 1e30;
+  std::pair<int, int> pick = cand[0];
+  for (const auto& cd : cand) {
+    c->set_schedule(cd.first, cd.second);
+    auto pair = [&]() -> whmc_status {
+      WHMC_TRY(hop(c, WHMC_F64, WHMC_L18, 0, 0, t, x, nullptr, 0.0, 1.0, nullptr));
+      return hop(c, WHMC_F64, WHMC_L18, 1, 0, x, t, nullptr, 0.0, 1.0, nullptr);
+    };
+    WHMC_TRY(pair());
+    WHMC_HIP(hipEventRecord(e0, c->stream));
+    for (int rep = 0; rep < 5; ++rep) WHMC_TRY(pair());
+    WHMC_HIP(hipEventRecord(e1, c->stream));
+    WHMC_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    WHMC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    const double per_hop = ms * 1e3 / 10.0;
+    if (per_hop < best) {
+      best = per_hop;
+      pick = cd;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->g = saved;
+  c->set_schedule(pick.first, pick.second);
+  if (pick.first == 1) c->hop_chunk = pick.second;
+  if (schedule) *schedule = c->g.sched;
+  if (chunk) *chunk = c->hop_chunk;
+  if (us) *us = best;
+  return WHMC_OK;
+}
+
 whmc_status whmc_set_option(whmc_ctx* c, int option, long long value) {
   WHMC_CHECK(c, WHMC_EARG, "whmc_set_option: null context");
   switch (option) {
     case WHMC_OPT_STREAM_THRESHOLD:
       WHMC_CHECK(value >= -1, WHMC_EARG, "whmc_set_option: the stream threshold must be >= -1");
       c->stream_threshold = value;
+      return WHMC_OK;
+    case WHMC_OPT_HOP_CHUNK:
+      WHMC_CHECK(c->g.nbs > 0 && value >= 1 && value <= c->g.nbs, WHMC_EARG,
+                 "whmc_set_option: the chunk must be 1 .. blocks per time slice (" + std::to_string(c->g.nbs) + ")");
+      c->hop_chunk = (int)value;
+      if (c->g.sched == 1) c->set_schedule(1, c->hop_chunk);
+      return WHMC_OK;
+    case WHMC_OPT_FORCE_KERNEL:
+      WHMC_CHECK(value == 0 || value == 1, WHMC_EARG, "whmc_set_option: the force kernel must be 0 or 1");
+      c->force_kernel = (int)value;
+      return WHMC_OK;
+    case WHMC_OPT_FORCE_CHUNK:
+      WHMC_CHECK(value >= 1 && value <= 24, WHMC_EARG, "whmc_set_option: pairs per force launch must be 1 .. 24");
+      c->force_chunk = (int)value;
+      return WHMC_OK;
+    case WHMC_OPT_HOP_SCHEDULE:
+      WHMC_CHECK(value == 0 || value == 1, WHMC_EARG, "whmc_set_option: the schedule must be 0 or 1");
+      WHMC_CHECK(c->set_schedule((int)value, c->hop_chunk), WHMC_EARG,
+                 "whmc_set_option: the time-slab schedule needs L_t divisible by 8 and time slices of whole "
+                 "128-site blocks");
       return WHMC_OK;
     default:
       set_error("whmc_set_option: unknown option " + std::to_string(option));
@@ -695,6 +848,10 @@ whmc_status whmc_get_option(const whmc_ctx* c, int option, long long* value) {
   WHMC_CHECK(c && value, WHMC_EARG, "whmc_get_option: null argument");
   switch (option) {
     case WHMC_OPT_STREAM_THRESHOLD: *value = c->stream_threshold; return WHMC_OK;
+    case WHMC_OPT_HOP_SCHEDULE: *value = c->g.sched; return WHMC_OK;
+    case WHMC_OPT_HOP_CHUNK: *value = c->hop_chunk; return WHMC_OK;
+    case WHMC_OPT_FORCE_KERNEL: *value = c->force_kernel; return WHMC_OK;
+    case WHMC_OPT_FORCE_CHUNK: *value = c->force_chunk; return WHMC_OK;
     default:
       set_error("whmc_get_option: unknown option " + std::to_string(option));
       return WHMC_EARG;

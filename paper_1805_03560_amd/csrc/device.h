@@ -12,6 +12,9 @@
 //   link  F32-18 : float2  [2][4] x 9 comps
 //   link  F32-12 : float4  [2][4] x 3 comps  rows 0,1 as 3 float4 (2 complex each)
 //   link  F16-12 : uint2   [2][4] x 3 comps  rows 0,1 as 3 x (4 halves = 2 complex)
+//   link  F64-8  : double2 [2][4] x 4 comps  U01, U02, U10, (phase of U00, phase of U20)
+//   link  F32-8  : float4  [2][4] x 2 comps  (U01, U02), (U10, phase of U00, phase of U20)
+//   link  F16-8  : uint4   [2][4] x 1 comp   8 halves: U01, U02, U10, phases / pi of U00 and U20
 // Link entries are bounded by 1 in modulus, so half precision links need no scale.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -90,6 +93,45 @@ template <typename R> WHMC_DEV void reconstruct_row2(SU3<R>& U) {
   U.e[2][2] = conj(cmul(U.e[0][0], U.e[1][1]) - cmul(U.e[0][1], U.e[1][0]));
 }
 
+// 8 real parameters per link, the form of Clark, Babich, Barros, Brower and Rebbi (Comput. Phys.
+// Commun. 181 (2010) 1517): U01, U02, one of U10 / U20 and the phases of U00 and of the other one.
+// Unit rows and columns give n = |U01|^2 + |U02|^2 = 1 - |U00|^2 = |U10|^2 + |U20|^2, hence the
+// moduli of U00 and of the entry stored by its phase; the other four entries follow from det U = 1,
+// which makes every entry the complex conjugate of its cofactor, together with the orthogonality
+// of column 0 to columns 1 and 2:
+//   U11 = -(conj(U00) U01 U10 + conj(U02) conj(U20)) / n,   U12 = (conj(U01) conj(U20) - conj(U00) U02 U10) / n,
+//   U21 = -(conj(U00) U01 U20 - conj(U02) conj(U10)) / n,   U22 = -(conj(U00) U02 U20 + conj(U01) conj(U10)) / n.
+// Of U10, U20 the one of smaller modulus is stored in full (FP64 and FP32): the other's modulus,
+// sqrt(n - |stored|^2) >= sqrt(n / 2), then suffers no cancellation.  The choice is flagged by
+// storing the phase plus 8 (phases lie in [-pi, pi]).  A link with n = 0 (U00 of modulus 1) has no
+// such form; the derivation of the format rejects fields with such links.
+WHMC_DEV void phase(double t, cplx<double>& e) { sincos(t, &e.im, &e.re); }
+WHMC_DEV void phase(float t, cplx<float>& e) { sincosf(t, &e.im, &e.re); }
+WHMC_DEV double rsq(double x) { return sqrt(x); }
+WHMC_DEV float rsq(float x) { return sqrtf(x); }
+
+// U.e[0][1], U.e[0][2] set; s = U10 (t_s < 4: phase of U20) or U20 (t_s = phase of U10 + 8)
+template <typename R> WHMC_DEV void reconstruct8(SU3<R>& U, cplx<R> s, R t00, R t_s) {
+  const cplx<R> a2 = U.e[0][1], a3 = U.e[0][2];
+  const R n = norm2(a2) + norm2(a3);
+  const bool swapped = t_s > R(4);
+  cplx<R> e00, eo;
+  phase(t00, e00);
+  phase(swapped ? t_s - R(8) : t_s, eo);
+  const cplx<R> a1 = rsq(fmax(R(1) - n, R(0))) * e00;
+  const cplx<R> o = rsq(fmax(n - norm2(s), R(0))) * eo;
+  const cplx<R> b1 = swapped ? o : s, c1 = swapped ? s : o;
+  const R inv = R(1) / n;
+  const cplx<R> ca1 = conj(a1), ca2 = conj(a2), ca3 = conj(a3), cb1 = conj(b1), cc1 = conj(c1);
+  U.e[0][0] = a1;
+  U.e[1][0] = b1;
+  U.e[2][0] = c1;
+  U.e[1][1] = -inv * (cmul(cmul(ca1, a2), b1) + cmul(ca3, cc1));
+  U.e[1][2] = inv * (cmul(ca2, cc1) - cmul(cmul(ca1, a3), b1));
+  U.e[2][1] = -inv * (cmul(cmul(ca1, a2), c1) - cmul(ca3, cb1));
+  U.e[2][2] = -inv * (cmul(cmul(ca1, a3), c1) + cmul(ca2, cb1));
+}
+
 // ------------------------------------------------------------------ geometry
 // dims L[0..3] = (L_t, L_z, L_y, L_x); direction mu is axis mu.  Checkerboard index
 // cb = lex / 2 with lex = ((t L_z + z) L_y + y) L_x + x.
@@ -99,6 +141,10 @@ struct Geom {
   int Lxh;   // L_x / 2
   int nbs;   // blocks per time slice for site_block (0: a slice is not a whole number of blocks)
   int xq;    // workgroups per XCD per time slice, ceil(nbs / 8); 0: plain eighths of the lattice
+  // single-RHS stencil schedule (site_block): 0 = slice ranges (site_block_xq); 1 = time slabs:
+  // XCD k owns the tx = L_t / 8 slices [k tx, (k + 1) tx) and sweeps them in chunks of tq blocks of
+  // a slice, all tx slices of a chunk before the next chunk (site_block_slab); nch = ceil(nbs / tq)
+  int sched, tx, tq, nch;
 };
 
 struct Coords {
@@ -201,13 +247,35 @@ WHMC_DEV int xcd_remap(int B, int nb) {
 // workgroups, g.xq = ceil(g.nbs / 8); a workgroup beyond its XCD's range gets the block index
 // L_t * g.nbs, whose sites all lie past the last site.  Otherwise (g.xq = 0, nb = ceil(Vh / block))
 // XCD k takes the k-th contiguous eighth of the blocks.
-WHMC_DEV int site_block(const Geom& g, int B, int nb) {
+WHMC_DEV int site_block_xq(const Geom& g, int B, int nb) {
   if (g.xq == 0) return xcd_remap(B, nb);
   const int k = B & 7, m = B >> 3;
   const int t = m / g.xq, j = m - t * g.xq;
   const int lo = k * g.nbs / 8, hi = (k + 1) * g.nbs / 8;
   if (lo + j >= hi) return g.L[0] * g.nbs;
   return t * g.nbs + lo + j;
+}
+
+// Time-slab schedule: XCD k owns the tx consecutive time slices starting at k tx and works through
+// them chunk by chunk, a chunk being tq consecutive blocks of a slice (a few z planes): the tx
+// slices of chunk 0, then of chunk 1, ...  A spinor is then read by its t +- 1 and z +- 1 neighbours
+// while it is in the same L2 (z neighbours across a chunk edge one chunk later), and only the two
+// slices at the slab's ends are also read by another XCD.  The grid has 8 tx nch tq workgroups;
+// one whose chunk runs past the slice's nbs blocks gets the block index L_t nbs (all sites past the
+// last one).
+WHMC_DEV int site_block_slab(const Geom& g, int B) {
+  const int k = B & 7, m = B >> 3;
+  const int per = g.tx * g.tq;
+  const int ch = m / per, r = m - ch * per;
+  const int t = r / g.tq, j = r - t * g.tq;
+  const int blk = ch * g.tq + j;
+  if (blk >= g.nbs) return g.L[0] * g.nbs;
+  return (k * g.tx + t) * g.nbs + blk;
+}
+
+// workgroup -> block of sites for the single-RHS stencil, solver and BiCGstab kernels
+WHMC_DEV int site_block(const Geom& g, int B, int nb) {
+  return g.sched == 1 ? site_block_slab(g, B) : site_block_xq(g, B, nb);
 }
 
 // G groups (e.g. of right-hand sides) per block of sites in one 1D grid of nb = G * (site grid)
@@ -241,7 +309,7 @@ WHMC_DEV int site_block_pair(const Geom& g, int B, int nb, int& par) {
     return b >> 1;
   }
   par = m & 1;
-  return site_block(g, ((m >> 1) << 3) | k, nb);
+  return site_block_xq(g, ((m >> 1) << 3) | k, nb);
 }
 
 // ------------------------------------------------------------------ AoSoA addressing
@@ -421,6 +489,54 @@ struct LinkF16_12T {
       U.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {h2f((unsigned short)(v.y & 0xffffu)), h2f((unsigned short)(v.y >> 16))};
     }
     reconstruct_row2(U);
+  }
+};
+
+template <bool NT = false>
+struct LinkF64_8T {
+  using Real = double;
+  const double2* p;
+  int Vh;
+  WHMC_DEV void load(int par, int mu, int i, SU3<double>& U) const {
+    const double2* q = p + (size_t)(par * 4 + mu) * 4 * Vh;
+    const double2 v0 = ldg<NT>(q + aos(0, i, 4, Vh)), v1 = ldg<NT>(q + aos(1, i, 4, Vh));
+    const double2 v2 = ldg<NT>(q + aos(2, i, 4, Vh)), v3 = ldg<NT>(q + aos(3, i, 4, Vh));
+    U.e[0][1] = {v0.x, v0.y};
+    U.e[0][2] = {v1.x, v1.y};
+    reconstruct8(U, cplx<double>{v2.x, v2.y}, v3.x, v3.y);
+  }
+};
+
+template <bool NT = false>
+struct LinkF32_8T {
+  using Real = float;
+  const float4* p;
+  int Vh;
+  WHMC_DEV void load(int par, int mu, int i, SU3<float>& U) const {
+    const float4* q = p + (size_t)(par * 4 + mu) * 2 * Vh;
+    const float4 v0 = ldg<NT>(q + aos(0, i, 2, Vh)), v1 = ldg<NT>(q + aos(1, i, 2, Vh));
+    U.e[0][1] = {v0.x, v0.y};
+    U.e[0][2] = {v0.z, v0.w};
+    reconstruct8(U, cplx<float>{v1.x, v1.y}, v1.z, v1.w);
+  }
+};
+
+// FP16: always U10 in full and the phase of U20 (halves of the phases / pi)
+template <bool NT = false>
+struct LinkF16_8T {
+  using Real = float;
+  const uint4* p;
+  int Vh;
+  WHMC_DEV void load(int par, int mu, int i, SU3<float>& U) const {
+    const uint4* q = p + (size_t)(par * 4 + mu) * Vh + aos(0, i, 1, Vh);
+    u4v w;
+    if (NT) w = __builtin_nontemporal_load((const u4v*)q);
+    else { const uint4 v = *q; w = u4v{v.x, v.y, v.z, v.w}; }
+    U.e[0][1] = {h2f((unsigned short)(w.x & 0xffffu)), h2f((unsigned short)(w.x >> 16))};
+    U.e[0][2] = {h2f((unsigned short)(w.y & 0xffffu)), h2f((unsigned short)(w.y >> 16))};
+    const cplx<float> b1 = {h2f((unsigned short)(w.z & 0xffffu)), h2f((unsigned short)(w.z >> 16))};
+    const float pi = 3.14159265358979f;
+    reconstruct8(U, b1, pi * h2f((unsigned short)(w.w & 0xffffu)), pi * h2f((unsigned short)(w.w >> 16)));
   }
 };
 

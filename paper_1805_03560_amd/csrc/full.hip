@@ -213,6 +213,7 @@ static whmc_status cg_full_impl(whmc_ctx* c, const Lnk& L, double* x, const doub
       const int k = std::min(check, prm->maxiter - total - pass_iters);
       if (k <= 0) break;
       for (int it = 0; it < k; ++it) {
+        TraceRange tr("whmc full-lattice cg iteration");
         hipLaunchKernelGGL((k_fullM<0, true, true, Lnk>), grid, block, 0, c->stream, c->g, L, half64(P, Vh, 0),
                            half64(P, Vh, 1), half64(T, Vh, 0), half64(T, Vh, 1), kappa, c->scal, c->red);
         hipLaunchKernelGGL(k_full_alpha, dim3(1), dim3(256), 0, c->stream, c->scal, c->red.partials, (int)grid.x);

@@ -297,6 +297,21 @@ WHMC_DEV void force_link(const Geom& g, int par, int i, const double2* U18, cons
   }
 }
 
+// Site-parallel form: one thread per site of either parity (both in one grid, the XCD that handles a
+// region does both of its parities) and the four links leaving the site, one after the other, so
+// the site's own X, Y of every pair are re-read by the same thread from its L1 instead of by four
+// workgroups.  The pairs of a launch (chunks of ctx->force_chunk) are summed per link first.
+__global__ __launch_bounds__(kBlock) void k_pf_force_site(Geom g, const double2* __restrict__ U18, PairPtrs P,
+                                                          int npairs, double kappa_eff, double* F, int accumulate) {
+  int par;
+  const int i = site_block_pair(g, blockIdx.x, gridDim.x >> 1, par) * kBlock + threadIdx.x;
+  if (i >= g.Vh) return;
+  force_link<0>(g, par, i, U18, P, npairs, kappa_eff, F, accumulate);
+  force_link<1>(g, par, i, U18, P, npairs, kappa_eff, F, accumulate);
+  force_link<2>(g, par, i, U18, P, npairs, kappa_eff, F, accumulate);
+  force_link<3>(g, par, i, U18, P, npairs, kappa_eff, F, accumulate);
+}
+
 __global__ __launch_bounds__(kBlock) void k_pf_force(Geom g, const double2* __restrict__ U18, PairPtrs P,
                                                      int npairs, double kappa_eff, double* F, int accumulate) {
   int par, mu;
@@ -314,9 +329,10 @@ whmc_status pf_force_pairs(whmc_ctx* c, double* F, const double* const* X_e, con
                            const double* const* Y_e, const double* const* Y_o, int npairs, double kappa_eff,
                            int accumulate) {
   WHMC_CHECK(c->gauge_loaded, WHMC_ESTATE, "no gauge field loaded");
+  const int chunk = c->force_chunk >= 1 && c->force_chunk <= 24 ? c->force_chunk : 24;
   int done = 0;
   while (done < npairs) {
-    const int n = npairs - done < 24 ? npairs - done : 24;
+    const int n = npairs - done < chunk ? npairs - done : chunk;
     PairPtrs P{};
     for (int k = 0; k < n; ++k) {
       P.Xe[k] = (const double2*)X_e[done + k];
@@ -324,9 +340,13 @@ whmc_status pf_force_pairs(whmc_ctx* c, double* F, const double* const* X_e, con
       P.Ye[k] = (const double2*)Y_e[done + k];
       P.Yo[k] = (const double2*)Y_o[done + k];
     }
-    const dim3 grid(8 * c->stencil_blocks());
-    hipLaunchKernelGGL(k_pf_force, grid, dim3(kBlock), 0, c->stream, c->g, c->U18, P, n, kappa_eff, F,
-                       (accumulate || done > 0) ? 1 : 0);
+    const int acc = (accumulate || done > 0) ? 1 : 0;
+    if (c->force_kernel == 1)
+      hipLaunchKernelGGL(k_pf_force_site, dim3(2 * c->stencil_blocks()), dim3(kBlock), 0, c->stream, c->g, c->U18, P,
+                         n, kappa_eff, F, acc);
+    else
+      hipLaunchKernelGGL(k_pf_force, dim3(8 * c->stencil_blocks()), dim3(kBlock), 0, c->stream, c->g, c->U18, P, n,
+                         kappa_eff, F, acc);
     WHMC_HIP(hipGetLastError());
     done += n;
   }

@@ -290,8 +290,11 @@ struct MDRun {
   std::vector<double> pending;
 
   whmc_status flush() {
+    static const char* names[] = {"whmc md P step, level 0", "whmc md P step, level 1", "whmc md P step, level 2",
+                                  "whmc md P step, level 3", "whmc md P step, level 4", "whmc md P step, level 5+"};
     for (size_t l = 0; l < lv.size(); ++l)
       if (pending[l] != 0.0) {
+        TraceRange tr(names[l < 5 ? l : 5]);
         WHMC_TRY(lv[l].force(-pending[l]));
         pending[l] = 0.0;
       }
@@ -299,6 +302,7 @@ struct MDRun {
   }
   whmc_status T(double eps) {
     WHMC_TRY(flush());
+    TraceRange tr("whmc md T step");
     return link_update(c, pi, eps);
   }
   whmc_status sub(int level, double span) {
@@ -359,6 +363,7 @@ whmc_status term_md(whmc_ctx* c, const TermAction& A, const TermMD& md, double* 
 // heat bath, H0, molecular dynamics, H1, Metropolis; the gauge field is restored on rejection
 whmc_status term_trajectory(whmc_ctx* c, const TermAction& A, const TermMD& md, const double* pi0, const double* eta,
                             double u, whmc_traj_result* res) {
+  TraceRange tr("whmc trajectory (multi-term)");
   const auto t0 = std::chrono::steady_clock::now();
   void *pi, *phi, *Usave;
   const size_t ab = (size_t)64 * c->Vh * sizeof(double);
@@ -510,6 +515,7 @@ whmc_status whmc_hmc_trajectory(whmc_ctx* c, const whmc_hmc_params* p, const dou
   WHMC_CHECK(c && pi0 && eta && res, WHMC_EARG, "whmc_hmc_trajectory: null argument");
   WHMC_TRY(check_hmc(p));
   WHMC_CHECK(c->gauge_loaded, WHMC_ESTATE, "no gauge field loaded");
+  TraceRange tr("whmc trajectory");
   const auto t0 = std::chrono::steady_clock::now();
   void *pi, *phi, *Usave;
   const size_t ab = (size_t)64 * c->Vh * sizeof(double);

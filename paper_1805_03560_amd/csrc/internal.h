@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/whmc.h"
 #include "device.h"
 
@@ -40,6 +42,15 @@ void set_error(const std::string& msg);
   } while (0)
 
 constexpr int kBlock = 128;   // threads per workgroup of the stencil and reduction kernels
+
+// roctx range over a host scope (solver iterations, MD steps, trajectories), seen by rocprofv3
+// --marker-trace; a no-op call when no tool is attached
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // per-solve scalar state that lives on the device so that iterations can be enqueued without a
 // host round trip; `done` / `pause` make the remaining queued kernels exit at once.
@@ -74,8 +85,11 @@ struct whmc_ctx {
   float2* U32_18 = nullptr;
   float4* U32_12 = nullptr;
   uint2* U16_12 = nullptr;
+  double2* U8 = nullptr;           // FP64 8-real
+  float4* U32_8 = nullptr;
+  uint4* U16_8 = nullptr;
   bool gauge_loaded = false;
-  bool derived_valid[4] = {false, false, false, false};  // U12, U32_18, U32_12, U16_12
+  bool derived_valid[7] = {};      // U12, U32_18, U32_12, U16_12, U8, U32_8, U16_8
   // scratch
   std::map<std::string, std::pair<void*, size_t>> ws;
   std::map<std::string, std::pair<int, double>> tuned;   // autotuned multi-RHS blockings (16 nb + lanes, us)
@@ -87,14 +101,31 @@ struct whmc_ctx {
   // than stream_threshold bytes; -1 = never, 0 = always.  Default 128 MiB; callers change it with
   // whmc_set_option(WHMC_OPT_STREAM_THRESHOLD).
   long long stream_threshold = 128LL << 20;
+  int hop_chunk = 0;   // tq of the time-slab schedule (WHMC_OPT_HOP_CHUNK)
+  int force_kernel = 0;   // pair-force kernel: 0 link-parallel, 1 site-parallel (WHMC_OPT_FORCE_KERNEL)
+  int force_chunk = 24;   // (X, Y) pairs per launch of the pair-force kernel (WHMC_OPT_FORCE_CHUNK)
   bool stream_links(int prec, int links) const {
     if (stream_threshold < 0) return false;
-    const long long per = prec == 0 ? (links == 18 ? 144 : 96) : (prec == 1 ? (links == 18 ? 72 : 48) : 24);
+    const long long per = links == 8 ? (prec == 0 ? 64 : prec == 1 ? 32 : 16)
+                                     : prec == 0 ? (links == 18 ? 144 : 96) : (prec == 1 ? (links == 18 ? 72 : 48) : 24);
     return (long long)8 * Vh * per > stream_threshold;
   }
   int num_blocks() const { return (Vh + whmc::kBlock - 1) / whmc::kBlock; }
-  // grid of the stencil kernels (site_block): may exceed num_blocks() by padding workgroups
+  // grid of the kernels on the slice-range schedule (site_block_xq, site_block_grp,
+  // site_block_pair): may exceed num_blocks() by padding workgroups
   int stencil_blocks() const { return g.xq ? 8 * g.xq * g.L[0] : num_blocks(); }
+  // grid of the single-RHS stencil kernels (site_block), for the schedule in g.sched
+  int site_blocks() const { return g.sched == 1 ? 8 * g.tx * g.nch * g.tq : stencil_blocks(); }
+  // time-slab schedule with chunks of tq blocks, if the lattice allows it (else false, unchanged)
+  bool set_schedule(int sched, int tq) {
+    if (sched == 0) { g.sched = 0; return true; }
+    if (sched != 1 || g.nbs == 0 || g.L[0] % 8 != 0 || tq < 1 || tq > g.nbs) return false;
+    g.sched = 1;
+    g.tx = g.L[0] / 8;
+    g.tq = tq;
+    g.nch = (g.nbs + tq - 1) / tq;
+    return true;
+  }
 };
 
 namespace whmc {

@@ -52,12 +52,23 @@ struct MLane {
 };
 
 template <int NB, int R>
-WHMC_DEV MLane<NB, R> mlane(const Geom& g, int G) {
+WHMC_DEV MLane<NB, R> mlane(const Geom& g, int G, int order) {
   constexpr int S = 64 / R;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  int u;
+  int u, sb;
   MLane<NB, R> m;
-  const int sb = site_block_grp(g, blockIdx.x, gridDim.x, G * R, u, m.slot);
+  if (order == 1) {
+    // group-major: the per = (site grid) * R workgroups of rhs group 0 sweep the lattice first,
+    // then those of group 1, ...; inside a group the R parts of a site block run back to back
+    const int per = gridDim.x / G;
+    const int grp = blockIdx.x / per;
+    int sub;
+    sb = site_block_grp(g, blockIdx.x - grp * per, per, R, sub, m.slot);
+    u = grp * R + sub;
+  } else {
+    // block-major: the G * R workgroups of a site block run back to back (links shared in L2)
+    sb = site_block_grp(g, blockIdx.x, gridDim.x, G * R, u, m.slot);
+  }
   const int grp = u / R;
   m.sub = u - grp * R;
   m.r0 = grp * R * NB;
@@ -199,34 +210,34 @@ WHMC_DEV void mhop_body(const Geom& g, int par, const MLane<NB, R>& m, const Lnk
 
 // plain multi-RHS hop: out_r = H_{par,1-par}^{(dag)} in_r
 template <int DAG, int NB, int R, class Lnk, class S>
-__global__ __launch_bounds__(kBlock) void k_mhop(Geom g, int par, int nrhs, int G, Lnk L, S in0, S out0) {
-  const MLane<NB, R> m = mlane<NB, R>(g, G);
+__global__ __launch_bounds__(kBlock) void k_mhop(Geom g, int par, int nrhs, int G, int order, Lnk L, S in0, S out0) {
+  const MLane<NB, R> m = mlane<NB, R>(g, G, order);
   if (m.i >= g.Vh) return;
   mhop_body<DAG>(g, par, m, L, in0, out0, AllRhs{nrhs});
 }
 
 // CG kernel 1: t = H_eo p
 template <int NB, int R, class Lnk, class S, class P>
-__global__ __launch_bounds__(kBlock) void k_mcg1(Geom g, int G, Lnk L, S p0, S t0, P live) {
-  const MLane<NB, R> m = mlane<NB, R>(g, G);
+__global__ __launch_bounds__(kBlock) void k_mcg1(Geom g, int G, int order, Lnk L, S p0, S t0, P live) {
+  const MLane<NB, R> m = mlane<NB, R>(g, G, order);
   if (m.i >= g.Vh) return;
   mhop_body<0>(g, 0, m, L, p0, t0, live);
 }
 
 // CG kernel 3: v = H^dag_eo u
 template <int NB, int R, class Lnk, class S, class P>
-__global__ __launch_bounds__(kBlock) void k_mcg3(Geom g, int G, Lnk L, S u0, S v0, P live) {
-  const MLane<NB, R> m = mlane<NB, R>(g, G);
+__global__ __launch_bounds__(kBlock) void k_mcg3(Geom g, int G, int order, Lnk L, S u0, S v0, P live) {
+  const MLane<NB, R> m = mlane<NB, R>(g, G, order);
   if (m.i >= g.Vh) return;
   mhop_body<1>(g, 0, m, L, u0, v0, live);
 }
 
 // CG kernel 2: u = p - kappa^2 H_oe t, |u|^2 = (p, A p)
 template <int NB, int R, class Lnk, class S, class P>
-__global__ __launch_bounds__(kBlock) void k_mcg2(Geom g, int nrhs, int G, Lnk L, S t0, S p0, S u0, K2 k2, P live,
+__global__ __launch_bounds__(kBlock) void k_mcg2(Geom g, int nrhs, int G, int order, Lnk L, S t0, S p0, S u0, K2 k2, P live,
                                                  Reduce red, int nslots) {
   using Re = typename S::Real;
-  const MLane<NB, R> m = mlane<NB, R>(g, G);
+  const MLane<NB, R> m = mlane<NB, R>(g, G, order);
   if (!any_live<R * NB>(live, m.r0)) return;   // uniform over the workgroup
   double nrm[NB];
 #pragma unroll
@@ -278,11 +289,11 @@ __global__ __launch_bounds__(256) void k_mcg2_fin(CGScalars* sc, int nrhs, const
 
 // CG kernel 4: A p = u - kappa^2 H^dag_oe v;  r -= alpha A p,  x += alpha p,  |r|^2
 template <int NB, int R, class Lnk, class S, class SR, bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_mcg4(Geom g, int nrhs, int G, Lnk L, S v0, S u0, S p0, SR rr0, SR x0,
+__global__ __launch_bounds__(kBlock) void k_mcg4(Geom g, int nrhs, int G, int order, Lnk L, S v0, S u0, S p0, SR rr0, SR x0,
                                                  K2 k2, CGScalars* sc, Reduce red, int nslots) {
   using Re = typename S::Real;
   using RR = typename SR::Real;
-  const MLane<NB, R> m = mlane<NB, R>(g, G);
+  const MLane<NB, R> m = mlane<NB, R>(g, G, order);
   const ByScalars live{sc, nrhs};
   if (!any_live<R * NB>(live, m.r0)) return;   // uniform over the workgroup
   double nrm[NB];
@@ -359,10 +370,10 @@ __global__ __launch_bounds__(256) void k_mcg4_fin(CGScalars* sc, int nrhs, const
 // FP64 residual of the host-chosen right-hand sides, last hop of M^dag M fused:
 // r_r = b_r - (u_r - kappa_r^2 H^dag_oe v_r), |r_r|^2 to the partial sums
 template <int R, class Lnk>
-__global__ __launch_bounds__(kBlock) void k_mres(Geom g, int nrhs, int G, Lnk L, SpinorF64 v0, SpinorF64 u0,
+__global__ __launch_bounds__(kBlock) void k_mres(Geom g, int nrhs, int G, int order, Lnk L, SpinorF64 v0, SpinorF64 u0,
                                                  SpinorF64 b0, SpinorF64 r0, K2 k2, BySet live, Reduce red,
                                                  int nslots) {
-  const MLane<1, R> m = mlane<1, R>(g, G);
+  const MLane<1, R> m = mlane<1, R>(g, G, order);
   if (!any_live<R>(live, m.r0)) return;   // uniform over the workgroup
   double nrm = 0.0;
   if (m.i < g.Vh && live(m.rb)) {
@@ -419,12 +430,14 @@ static SpinorF32 h32(void* p, int Vh) { return SpinorF32{(float4*)p, Vh}; }
 static SpinorF16 h16(void* p, int Vh) { return SpinorF16{(uint4*)p, (float*)((uint4*)p + (size_t)3 * Vh), Vh}; }
 static size_t field_bytes(int prec, int Vh) { return (size_t)Vh * (prec == WHMC_F64 ? 192 : prec == WHMC_F32 ? 96 : 52); }
 
-// Blocking of the multi-RHS kernels: NB right-hand sides per thread (register block) and R lanes
-// per site sharing each link load.  FP64 keeps NB = 1 (its single-rhs hop already fills the
-// register file); the low-precision formats, whose cost per site is dominated by link decoding,
-// also block in registers.
+// Blocking of the multi-RHS kernels: NB right-hand sides per thread (register block), R lanes
+// per site sharing each link load, and the order of the workgroups: 0 = block-major (all groups of
+// right-hand sides of a site block back to back, links reused from L2), 1 = group-major (each group
+// of R * NB right-hand sides sweeps the lattice before the next: the neighbour spinors of the group
+// stay in L2 while the links are read once per group).  FP64 keeps NB = 1 (its single-rhs hop
+// already fills the register file); the low-precision formats also block in registers.
 struct Blocking {
-  int nb, lanes;
+  int nb, lanes, order;
 };
 
 template <class Lnk>
@@ -440,6 +453,8 @@ static whmc_status with_blocking(Blocking b, F&& f) {
     if (b.nb == 1 && b.lanes == 1) return f(I1{}, I1{});
     if (b.nb == 1 && b.lanes == 2) return f(I1{}, I2{});
     if (b.nb == 1 && b.lanes == 4) return f(I1{}, I4{});
+    if (b.nb == 2 && b.lanes == 1) return f(I2{}, I1{});
+    if (b.nb == 2 && b.lanes == 2) return f(I2{}, I2{});
   } else {
     if (b.nb == 1 && b.lanes == 1) return f(I1{}, I1{});
     if (b.nb == 1 && b.lanes == 2) return f(I1{}, I2{});
@@ -448,8 +463,8 @@ static whmc_status with_blocking(Blocking b, F&& f) {
     if (b.nb == 4 && b.lanes == 1) return f(I4{}, I1{});
     if (b.nb == 4 && b.lanes == 2) return f(I4{}, I2{});
   }
-  set_error("multi-RHS blocking: FP64 takes rhs_block 1 with rhs_lanes 1, 2 or 4; FP32 / FP16 take rhs_block 1, 2 "
-            "or 4 with rhs_lanes 1 or 2");
+  set_error("multi-RHS blocking: FP64 takes rhs_block 1 with rhs_lanes 1, 2 or 4, or rhs_block 2 with rhs_lanes 1 or 2; "
+            "FP32 / FP16 take rhs_block 1, 2 or 4 with rhs_lanes 1 or 2");
   return WHMC_EARG;
 }
 
@@ -458,23 +473,26 @@ static std::vector<Blocking> candidates(int prec, int nrhs) {
   std::vector<Blocking> out;
   const int nbs[3] = {1, 2, 4}, ls[3] = {1, 2, 4};
   for (int nb : nbs) {
-    if (prec == WHMC_F64 && nb > 1) break;
+    if (prec == WHMC_F64 && nb > 2) break;
     for (int l : ls) {
-      if (prec != WHMC_F64 && l > 2) break;
+      if ((prec != WHMC_F64 || nb > 1) && l > 2) break;
       const int group = nb * l;
       if (group > 1 && group / 2 >= nrhs) continue;   // wider than needed: idle lanes or registers
-      out.push_back({nb, l});
+      out.push_back({nb, l, 0});
+      if (nrhs > group) out.push_back({nb, l, 1});      // several groups: try group-major too
     }
   }
   return out;
 }
 
 template <int NB, int R, class Lnk, class S>
-static void launch_mhop(whmc_ctx* c, int par, int dag, int nrhs, const Lnk& L, S in, S out) {
+static void launch_mhop(whmc_ctx* c, int par, int dag, int nrhs, int order, const Lnk& L, S in, S out) {
   const int G = (nrhs + R * NB - 1) / (R * NB);
   const dim3 grid(c->stencil_blocks() * G * R), block(kBlock);
-  if (dag) hipLaunchKernelGGL((k_mhop<1, NB, R, Lnk, S>), grid, block, 0, c->stream, c->g, par, nrhs, G, L, in, out);
-  else hipLaunchKernelGGL((k_mhop<0, NB, R, Lnk, S>), grid, block, 0, c->stream, c->g, par, nrhs, G, L, in, out);
+  if (dag)
+    hipLaunchKernelGGL((k_mhop<1, NB, R, Lnk, S>), grid, block, 0, c->stream, c->g, par, nrhs, G, order, L, in, out);
+  else
+    hipLaunchKernelGGL((k_mhop<0, NB, R, Lnk, S>), grid, block, 0, c->stream, c->g, par, nrhs, G, order, L, in, out);
 }
 
 // dispatch on precision / link format / cache policy; f(L, S-maker) is called with the typed link
@@ -508,7 +526,7 @@ static whmc_status mhop(whmc_ctx* c, int prec, int links, int par, int dag, int 
                         const void* in) {
   WHMC_TRY(with_format(c, prec, links, [&](auto L, auto mk) {
     return with_blocking<decltype(L)>(b, [&](auto nb, auto lanes) {
-      launch_mhop<decltype(nb)::value, decltype(lanes)::value>(c, par, dag, nrhs, L, mk((void*)in, c->Vh),
+      launch_mhop<decltype(nb)::value, decltype(lanes)::value>(c, par, dag, nrhs, b.order, L, mk((void*)in, c->Vh),
                                                                 mk(out, c->Vh));
       return WHMC_OK;
     });
@@ -522,8 +540,9 @@ static whmc_status autotune_blocking(whmc_ctx* c, int prec, int links, int nrhs,
   const std::string key = std::to_string(prec) + "/" + std::to_string(links) + "/" + std::to_string(nrhs);
   auto it = c->tuned.find(key);
   if (it != c->tuned.end()) {
-    best->nb = it->second.first / 16;
-    best->lanes = it->second.first % 16;
+    best->nb = it->second.first / 256;
+    best->lanes = (it->second.first / 16) % 16;
+    best->order = it->second.first % 16;
     if (best_us) *best_us = it->second.second;
     return WHMC_OK;
   }
@@ -535,7 +554,7 @@ static whmc_status autotune_blocking(whmc_ctx* c, int prec, int links, int nrhs,
   hipEvent_t e0, e1;
   WHMC_HIP(hipEventCreate(&e0));
   WHMC_HIP(hipEventCreate(&e1));
-  Blocking bb{1, 1};
+  Blocking bb{1, 1, 0};
   double bt = 1e30;
   for (const Blocking& b : candidates(prec, nrhs)) {
     WHMC_TRY(mhop(c, prec, links, 0, 0, nrhs, b, out, in));   // warm-up
@@ -553,17 +572,21 @@ static whmc_status autotune_blocking(whmc_ctx* c, int prec, int links, int nrhs,
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  c->tuned[key] = {bb.nb * 16 + bb.lanes, bt};
+  c->tuned[key] = {bb.nb * 256 + bb.lanes * 16 + bb.order, bt};
   *best = bb;
   if (best_us) *best_us = bt;
   return WHMC_OK;
 }
 
-// the blocking a call asks for: both 0 = autotuned, else the given values (0 read as 1)
-static whmc_status resolve_blocking(whmc_ctx* c, int prec, int links, int nrhs, int nb, int lanes, Blocking* b) {
+// the blocking a call asks for: nb = lanes = 0 = autotuned (order included), else the given values
+// (0 read as 1) with the given order
+static whmc_status resolve_blocking(whmc_ctx* c, int prec, int links, int nrhs, int nb, int lanes, int order,
+                                    Blocking* b) {
   if (nb <= 0 && lanes <= 0) return autotune_blocking(c, prec, links, nrhs, b, nullptr);
+  WHMC_CHECK(order == 0 || order == 1, WHMC_EARG, "multi-RHS order must be 0 (block-major) or 1 (group-major)");
   b->nb = nb > 0 ? nb : 1;
   b->lanes = lanes > 0 ? lanes : 1;
+  b->order = order;
   return WHMC_OK;
 }
 
@@ -664,17 +687,21 @@ __global__ __launch_bounds__(kBlock) void k_mrel_p(int Vh, S p, SR r, const doub
 }
 
 template <int NB, int R, bool MIXED, class Lnk, class S, class SR>
-static void enqueue_multi(whmc_ctx* c, int nrhs, const Lnk& L, S p, S t, S u, S v, SR r, SR x, const K2& k2, int n) {
+static void enqueue_multi(whmc_ctx* c, int nrhs, int order, const Lnk& L, S p, S t, S u, S v, SR r, SR x, const K2& k2,
+                          int n) {
   const int G = (nrhs + R * NB - 1) / (R * NB), ns = c->stencil_blocks();
   const dim3 grid(ns * G * R), block(kBlock), grid5(c->num_blocks(), nrhs);
   const ByScalars live{c->scal, nrhs};
   for (int it = 0; it < n; ++it) {
-    hipLaunchKernelGGL((k_mcg1<NB, R, Lnk, S, ByScalars>), grid, block, 0, c->stream, c->g, G, L, p, t, live);
-    hipLaunchKernelGGL((k_mcg2<NB, R, Lnk, S, ByScalars>), grid, block, 0, c->stream, c->g, nrhs, G, L, t, p, u, k2,
+    TraceRange tr("whmc multi-rhs cg iteration");
+    hipLaunchKernelGGL((k_mcg1<NB, R, Lnk, S, ByScalars>), grid, block, 0, c->stream, c->g, G, order, L, p, t, live);
+    hipLaunchKernelGGL((k_mcg2<NB, R, Lnk, S, ByScalars>), grid, block, 0, c->stream, c->g, nrhs, G, order, L, t, p, u,
+                       k2,
                        live, c->red, ns);
     hipLaunchKernelGGL(k_mcg2_fin, dim3(nrhs), dim3(256), 0, c->stream, c->scal, nrhs, c->red.partials, ns * R);
-    hipLaunchKernelGGL((k_mcg3<NB, R, Lnk, S, ByScalars>), grid, block, 0, c->stream, c->g, G, L, u, v, live);
-    hipLaunchKernelGGL((k_mcg4<NB, R, Lnk, S, SR, MIXED>), grid, block, 0, c->stream, c->g, nrhs, G, L, v, u, p, r, x,
+    hipLaunchKernelGGL((k_mcg3<NB, R, Lnk, S, ByScalars>), grid, block, 0, c->stream, c->g, G, order, L, u, v, live);
+    hipLaunchKernelGGL((k_mcg4<NB, R, Lnk, S, SR, MIXED>), grid, block, 0, c->stream, c->g, nrhs, G, order, L, v, u, p,
+                       r, x,
                        k2, c->scal, c->red, ns);
     hipLaunchKernelGGL(k_mcg4_fin<MIXED>, dim3(nrhs), dim3(256), 0, c->stream, c->scal, nrhs, c->red.partials,
                        ns * R);
@@ -686,16 +713,18 @@ static void enqueue_multi(whmc_ctx* c, int nrhs, const Lnk& L, S p, S t, S u, S 
 // through the multi-RHS kernels (one pass over the links serves all of them); |r_r|^2 lands in
 // rr_dev[r].  t, u, v, r64 are FP64 scratch of nrhs half fields each.
 template <int R, class Lnk>
-static void enqueue_residual(whmc_ctx* c, unsigned mask, int nrhs, const Lnk& L, SpinorF64 x, SpinorF64 b,
+static void enqueue_residual(whmc_ctx* c, unsigned mask, int nrhs, int order, const Lnk& L, SpinorF64 x, SpinorF64 b,
                              const K2& k2, SpinorF64 t, SpinorF64 u, SpinorF64 v, SpinorF64 r64, double* rr_dev) {
   const int G = (nrhs + R - 1) / R, ns = c->stencil_blocks();
   const dim3 grid(ns * G * R), block(kBlock);
   const BySet live{mask, nrhs};
-  hipLaunchKernelGGL((k_mcg1<1, R, Lnk, SpinorF64, BySet>), grid, block, 0, c->stream, c->g, G, L, x, t, live);
-  hipLaunchKernelGGL((k_mcg2<1, R, Lnk, SpinorF64, BySet>), grid, block, 0, c->stream, c->g, nrhs, G, L, t, x, u, k2,
+  hipLaunchKernelGGL((k_mcg1<1, R, Lnk, SpinorF64, BySet>), grid, block, 0, c->stream, c->g, G, order, L, x, t, live);
+  hipLaunchKernelGGL((k_mcg2<1, R, Lnk, SpinorF64, BySet>), grid, block, 0, c->stream, c->g, nrhs, G, order, L, t, x,
+                     u, k2,
                      live, c->red, ns);
-  hipLaunchKernelGGL((k_mcg3<1, R, Lnk, SpinorF64, BySet>), grid, block, 0, c->stream, c->g, G, L, u, v, live);
-  hipLaunchKernelGGL((k_mres<R, Lnk>), grid, block, 0, c->stream, c->g, nrhs, G, L, v, u, b, r64, k2, live, c->red,
+  hipLaunchKernelGGL((k_mcg3<1, R, Lnk, SpinorF64, BySet>), grid, block, 0, c->stream, c->g, G, order, L, u, v, live);
+  hipLaunchKernelGGL((k_mres<R, Lnk>), grid, block, 0, c->stream, c->g, nrhs, G, order, L, v, u, b, r64, k2, live,
+                     c->red,
                      ns);
   hipLaunchKernelGGL(k_mres_fin, dim3(nrhs), dim3(256), 0, c->stream, live, c->red.partials, ns * R, rr_dev);
 }
@@ -708,7 +737,8 @@ static whmc_status residual_multi(whmc_ctx* c, unsigned mask, int nrhs, const do
   auto run = [&](auto L) {
     return with_blocking<decltype(L)>(bk, [&](auto nb, auto lanes) {
       (void)nb;
-      enqueue_residual<decltype(lanes)::value>(c, mask, nrhs, L, h64((void*)x, Vh), h64((void*)b, Vh), k2, h64(t, Vh),
+      enqueue_residual<decltype(lanes)::value>(c, mask, nrhs, bk.order, L, h64((void*)x, Vh), h64((void*)b, Vh), k2,
+                                               h64(t, Vh),
                                                h64(u, Vh), h64(v, Vh), h64(r64, Vh), rr_dev);
       return WHMC_OK;
     });
@@ -725,7 +755,7 @@ whmc_status cg_solve_multi(whmc_ctx* c, double* x, const double* b, const double
   const bool mixed = prm->prec != WHMC_F64;
   const int prec = prm->prec;
   const int links = prm->links;
-  if (mixed && links != WHMC_L12) {
+  if ((mixed && links != WHMC_L12) || links == WHMC_L8) {
     // no multi-RHS kernels for this format: solve the right-hand sides one after the other
     whmc_cg_params one = *prm;
     whmc_status worst = WHMC_OK;
@@ -743,7 +773,7 @@ whmc_status cg_solve_multi(whmc_ctx* c, double* x, const double* b, const double
   const int rprec = mixed ? WHMC_F32 : WHMC_F64;
   const size_t rb = field_bytes(rprec, Vh);
   Blocking bk;
-  WHMC_TRY(resolve_blocking(c, prec, links, nrhs, prm->rhs_block, prm->rhs_lanes, &bk));
+  WHMC_TRY(resolve_blocking(c, prec, links, nrhs, prm->rhs_block, prm->rhs_lanes, prm->rhs_order, &bk));
   void *p, *t, *u, *v, *rs, *xs, *r64, *ft, *fu, *fv;
   WHMC_TRY(workspace(c, "m_p", sb * nrhs, &p));
   WHMC_TRY(workspace(c, "m_t", sb * nrhs, &t));
@@ -800,10 +830,10 @@ whmc_status cg_solve_multi(whmc_ctx* c, double* x, const double* b, const double
           constexpr int NB = decltype(nbc)::value, R = decltype(lanes)::value;
           // FP64 links run the plain FP64 CG, low-precision links the mixed one
           if constexpr (is_f64_links<decltype(L)>())
-            enqueue_multi<NB, R, false>(c, nrhs, L, mk(p, Vh), mk(t, Vh), mk(u, Vh), mk(v, Vh), h64(rs, Vh),
+            enqueue_multi<NB, R, false>(c, nrhs, bk.order, L, mk(p, Vh), mk(t, Vh), mk(u, Vh), mk(v, Vh), h64(rs, Vh),
                                         h64(xs, Vh), k2, check);
           else
-            enqueue_multi<NB, R, true>(c, nrhs, L, mk(p, Vh), mk(t, Vh), mk(u, Vh), mk(v, Vh), h32(rs, Vh),
+            enqueue_multi<NB, R, true>(c, nrhs, bk.order, L, mk(p, Vh), mk(t, Vh), mk(u, Vh), mk(v, Vh), h32(rs, Vh),
                                        h32(xs, Vh), k2, check);
           return WHMC_OK;
         });
@@ -921,23 +951,23 @@ whmc_status cg_solve_multi(whmc_ctx* c, double* x, const double* b, const double
 using namespace whmc;
 
 extern "C" whmc_status whmc_apply_H_multi(whmc_ctx* c, void* out, const void* in, int out_parity, int dagger,
-                                          int prec, int links, int nrhs, int rhs_block, int rhs_lanes) {
+                                          int prec, int links, int nrhs, int rhs_block, int rhs_lanes, int rhs_order) {
   WHMC_CHECK(c && out && in && out != in, WHMC_EARG, "whmc_apply_H_multi: bad pointers");
   WHMC_CHECK(out_parity == 0 || out_parity == 1, WHMC_EARG, "whmc_apply_H_multi: out_parity must be 0 or 1");
   WHMC_CHECK(nrhs >= 1 && nrhs <= kMaxRhs, WHMC_EARG, "whmc_apply_H_multi: nrhs must be in [1, 16]");
   Blocking b;
-  WHMC_TRY(resolve_blocking(c, prec, links, nrhs, rhs_block, rhs_lanes, &b));
+  WHMC_TRY(resolve_blocking(c, prec, links, nrhs, rhs_block, rhs_lanes, rhs_order, &b));
   return mhop(c, prec, links, out_parity, dagger ? 1 : 0, nrhs, b, out, in);
 }
 
 extern "C" whmc_status whmc_autotune(whmc_ctx* c, int prec, int links, int nrhs, int* rhs_block, int* rhs_lanes,
-                                     double* us) {
+                                     int* rhs_order, double* us) {
   WHMC_CHECK(c && rhs_block && rhs_lanes, WHMC_EARG, "whmc_autotune: null argument");
   WHMC_CHECK(nrhs >= 1 && nrhs <= kMaxRhs, WHMC_EARG, "whmc_autotune: nrhs must be in [1, 16]");
   Blocking b;
   WHMC_TRY(autotune_blocking(c, prec, links, nrhs, &b, us));
   *rhs_block = b.nb;
   *rhs_lanes = b.lanes;
+  if (rhs_order) *rhs_order = b.order;
   return WHMC_OK;
 }
-

@@ -17,11 +17,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libwhmc.so")
 
 F64, F32, F16 = 0, 1, 2
-L12, L18 = 12, 18
+L8, L12, L18 = 8, 12, 18
 LEAPFROG, OMELYAN = 0, 1
 FORCE_PF, FORCE_GAUGE, FORCE_ACCUMULATE = 1, 2, 4
 _STATUS = {0: "OK", 1: "EARG", 2: "EHIP", 3: "ENOCONV", 4: "EUNSUP", 5: "ENOTSU3", 6: "ESTATE", 7: "ENONFINITE"}
-OPT_STREAM_THRESHOLD = 1
+OPT_STREAM_THRESHOLD, OPT_HOP_SCHEDULE, OPT_HOP_CHUNK, OPT_FORCE_KERNEL, OPT_FORCE_CHUNK = 1, 2, 3, 4, 5
 _HALF_BYTES = {F64: 192, F32: 96, F16: 52}
 
 
@@ -34,7 +34,7 @@ class WhmcError(RuntimeError):
 class CGParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("prec", ctypes.c_int),
                 ("links", ctypes.c_int), ("delta", ctypes.c_double), ("check_every", ctypes.c_int),
-                ("rhs_block", ctypes.c_int), ("rhs_lanes", ctypes.c_int)]
+                ("rhs_block", ctypes.c_int), ("rhs_lanes", ctypes.c_int), ("rhs_order", ctypes.c_int)]
 
 
 class CGStats(ctypes.Structure):
@@ -112,8 +112,9 @@ def rooted(N, ns, k=0, n_t=0, n_max=0):
                   int(n_max))
 
 
-def cg_params(tol=1e-10, maxiter=10000, prec=F64, links=L18, delta=0.1, check_every=8, rhs_block=0, rhs_lanes=0):
-    return CGParams(tol, maxiter, prec, links, delta, check_every, rhs_block, rhs_lanes)
+def cg_params(tol=1e-10, maxiter=10000, prec=F64, links=L18, delta=0.1, check_every=8, rhs_block=0, rhs_lanes=0,
+              rhs_order=0):
+    return CGParams(tol, maxiter, prec, links, delta, check_every, rhs_block, rhs_lanes, rhs_order)
 
 
 _lib = None
@@ -126,6 +127,8 @@ _SIGS = {
     "whmc_set_stream": ([_P, _P], ctypes.c_int),
     "whmc_set_option": ([_P, ctypes.c_int, ctypes.c_longlong], ctypes.c_int),
     "whmc_get_option": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
+    "whmc_autotune_hop": ([_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                           ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "whmc_field_bytes": ([_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "whmc_load_gauge": ([_P, _P, ctypes.c_double], ctypes.c_int),
     "whmc_export_gauge": ([_P, _P], ctypes.c_int),
@@ -137,9 +140,10 @@ _SIGS = {
     "whmc_apply_H": ([_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "whmc_apply_Moo": ([_P, _P, _P, ctypes.c_double, ctypes.c_int], ctypes.c_int),
     "whmc_apply_H_multi": ([_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                            ctypes.c_int, ctypes.c_int], ctypes.c_int),
+                            ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "whmc_autotune": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
-                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)],
+                      ctypes.c_int),
     "whmc_bicgstab_solve": ([_P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.POINTER(CGParams),
                              ctypes.POINTER(CGStats)], ctypes.c_int),
     "whmc_apply_MdagM": ([_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int], ctypes.c_int),
@@ -357,18 +361,19 @@ class Context:
         return out
 
     def apply_H_multi(self, inp, out_parity, nrhs, dagger=False, prec=F64, links=L18, rhs_block=0, rhs_lanes=0,
-                      out=None):
+                      rhs_order=0, out=None):
         if out is None:
             out = self.half_spinor(prec, nrhs)
         _check(lib().whmc_apply_H_multi(self._h, _ptr(out), _ptr(inp), out_parity, int(dagger), prec, links, nrhs,
-                                        rhs_block, rhs_lanes))
+                                        rhs_block, rhs_lanes, rhs_order))
         return out
 
     def autotune(self, prec, links, nrhs):
-        """-> (rhs_block, rhs_lanes, microseconds per launch) of the fastest multi-RHS blocking"""
-        nb, lanes, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
-        _check(lib().whmc_autotune(self._h, prec, links, nrhs, ctypes.byref(nb), ctypes.byref(lanes), ctypes.byref(us)))
-        return nb.value, lanes.value, us.value
+        """-> (rhs_block, rhs_lanes, rhs_order, microseconds per launch) of the fastest multi-RHS blocking"""
+        nb, lanes, order, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(lib().whmc_autotune(self._h, prec, links, nrhs, ctypes.byref(nb), ctypes.byref(lanes),
+                                   ctypes.byref(order), ctypes.byref(us)))
+        return nb.value, lanes.value, order.value, us.value
 
     def apply_Moo(self, inp, kappa, dagger=False, out=None):
         out = self.half_spinor() if out is None else out
@@ -410,6 +415,12 @@ class Context:
         _check(lib().whmc_force_full(self._h, _ptr(out), _ptr(phi), float(kappa), float(beta),
                                      ctypes.byref(solver) if solver is not None else None, int(flags)))
         return out
+
+    def autotune_hop(self):
+        """-> (schedule, chunk, microseconds per hop) of the fastest single-RHS stencil schedule"""
+        sc, ch, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(lib().whmc_autotune_hop(self._h, ctypes.byref(sc), ctypes.byref(ch), ctypes.byref(us)))
+        return sc.value, ch.value, us.value
 
     def set_option(self, option, value):
         _check(lib().whmc_set_option(self._h, int(option), int(value)))

@@ -17,16 +17,18 @@ LOW_PREC_BLOCKINGS = [(1, 1), (1, 2), (2, 1), (2, 2), (4, 1), (4, 2)]
 
 
 @pytest.mark.parametrize("nrhs", [1, 3, 5])
-@pytest.mark.parametrize("lanes", [1, 2, 4])
+@pytest.mark.parametrize("nb,lanes", [(1, 1), (1, 2), (1, 4), (2, 1), (2, 2)])
+@pytest.mark.parametrize("order", [0, 1])
 # (4, 8, 16, 16): time slices of 8 blocks, one per XCD; (4, 12, 16, 16): 12 blocks, with padding
 @pytest.mark.parametrize("dims", [(4, 4, 6, 6), (4, 8, 16, 16), (4, 12, 16, 16)])
-def test_multi_hop_fp64_parity(nrhs, lanes, dims):
+def test_multi_hop_fp64_parity(nrhs, nb, lanes, order, dims):
     lat = Lattice(dims)
     U = synth.haar_links(dims, 5000)
     xs = np.stack([synth.gaussian_spinor(lat.Vh, 5001 + r) for r in range(nrhs)])
     ctx = make_ctx(dims, U)
     for par, dag in [(0, 0), (1, 1)]:
-        out = ctx.apply_H_multi(pack_half(ctx, xs), par, nrhs, dagger=dag, rhs_block=1, rhs_lanes=lanes)
+        out = ctx.apply_H_multi(pack_half(ctx, xs), par, nrhs, dagger=dag, rhs_block=nb, rhs_lanes=lanes,
+                                rhs_order=order)
         got = unpack_half(ctx, out, nrhs).reshape(nrhs, lat.Vh, 4, 3)
         for r in range(nrhs):
             assert rel_err(got[r], dirac.apply_Hblock(lat, U, xs[r], par, dagger=bool(dag))) < 1e-12
@@ -42,24 +44,26 @@ def test_multi_hop_low_precision(prec, tol):
     ctx = make_ctx(dims, U)
     xin = ctx.convert_spinor(pack_half(ctx, xs), whmc.F64, prec, nrhs)
     for nb, lanes in LOW_PREC_BLOCKINGS:
-        out = ctx.apply_H_multi(xin, 1, nrhs, prec=prec, links=whmc.L12, rhs_block=nb, rhs_lanes=lanes)
-        got = unpack_half(ctx, ctx.convert_spinor(out, prec, whmc.F64, nrhs), nrhs).reshape(nrhs, lat.Vh, 4, 3)
-        for r in range(nrhs):
-            assert rel_err(got[r], dirac.apply_Hblock(lat, U, xs[r], 1)) < tol
+        for order in (0, 1):
+            out = ctx.apply_H_multi(xin, 1, nrhs, prec=prec, links=whmc.L12, rhs_block=nb, rhs_lanes=lanes,
+                                    rhs_order=order)
+            got = unpack_half(ctx, ctx.convert_spinor(out, prec, whmc.F64, nrhs), nrhs).reshape(nrhs, lat.Vh, 4, 3)
+            for r in range(nrhs):
+                assert rel_err(got[r], dirac.apply_Hblock(lat, U, xs[r], 1)) < tol
 
 
 def test_autotuner_returns_a_valid_block():
     dims = (8, 8, 8, 8)
     ctx = make_ctx(dims, synth.smooth_links(dims, 5020))
-    nb, lanes, us = ctx.autotune(whmc.F64, whmc.L18, 8)
-    assert nb == 1 and lanes in (1, 2, 4) and us > 0
-    assert ctx.autotune(whmc.F64, whmc.L18, 8)[:2] == (nb, lanes)     # remembered
-    nb, lanes, us = ctx.autotune(whmc.F16, whmc.L12, 8)
-    assert (nb, lanes) in LOW_PREC_BLOCKINGS and us > 0
+    nb, lanes, order, us = ctx.autotune(whmc.F64, whmc.L18, 8)
+    assert (nb, lanes) in [(1, 1), (1, 2), (1, 4), (2, 1), (2, 2)] and order in (0, 1) and us > 0
+    assert ctx.autotune(whmc.F64, whmc.L18, 8)[:3] == (nb, lanes, order)     # remembered
+    nb, lanes, order, us = ctx.autotune(whmc.F16, whmc.L12, 8)
+    assert (nb, lanes) in LOW_PREC_BLOCKINGS and order in (0, 1) and us > 0
 
 
-@pytest.mark.parametrize("prec,nb,lanes", [(whmc.F64, 2, 1), (whmc.F64, 1, 3), (whmc.F64, 1, 8), (whmc.F32, 3, 1),
-                                           (whmc.F16, 4, 4)])
+@pytest.mark.parametrize("prec,nb,lanes", [(whmc.F64, 4, 1), (whmc.F64, 2, 4), (whmc.F64, 1, 3), (whmc.F64, 1, 8),
+                                           (whmc.F32, 3, 1), (whmc.F16, 4, 4)])
 def test_unsupported_blocking_rejected(prec, nb, lanes):
     dims = (4, 4, 4, 4)
     lat = Lattice(dims)
@@ -72,19 +76,20 @@ def test_unsupported_blocking_rejected(prec, nb, lanes):
     assert e.value.status == 1   # EARG
 
 
-@pytest.mark.parametrize("prec,nrhs,nb,lanes,dims", [(whmc.F64, 4, 0, 0, (4, 4, 4, 8)), (whmc.F64, 5, 1, 2, (4, 4, 4, 8)),
-                                                     (whmc.F32, 4, 0, 0, (4, 4, 4, 8)), (whmc.F16, 6, 4, 2, (4, 4, 4, 8)),
-                                                     (whmc.F32, 5, 2, 1, (4, 4, 4, 8)),
-                                                     (whmc.F64, 2, 1, 4, (4, 8, 16, 16)),
-                                                     (whmc.F32, 3, 2, 2, (4, 12, 16, 16))])
-def test_masked_multi_rhs_cg(prec, nrhs, nb, lanes, dims):
+@pytest.mark.parametrize("prec,nrhs,nb,lanes,order,dims", [
+    (whmc.F64, 4, 0, 0, 0, (4, 4, 4, 8)), (whmc.F64, 5, 1, 2, 0, (4, 4, 4, 8)), (whmc.F32, 4, 0, 0, 0, (4, 4, 4, 8)),
+    (whmc.F16, 6, 4, 2, 0, (4, 4, 4, 8)), (whmc.F32, 5, 2, 1, 0, (4, 4, 4, 8)), (whmc.F64, 2, 1, 4, 0, (4, 8, 16, 16)),
+    (whmc.F32, 3, 2, 2, 0, (4, 12, 16, 16)), (whmc.F64, 5, 2, 1, 0, (4, 8, 16, 16)), (whmc.F64, 6, 2, 2, 1, (4, 4, 4, 8)),
+    # group-major order: several groups of right-hand sides, each sweeping the lattice in turn
+    (whmc.F64, 7, 1, 2, 1, (4, 8, 16, 16)), (whmc.F16, 9, 2, 2, 1, (4, 12, 16, 16)), (whmc.F32, 5, 1, 1, 1, (4, 4, 4, 8))])
+def test_masked_multi_rhs_cg(prec, nrhs, nb, lanes, order, dims):
     lat = Lattice(dims)
     U = synth.smooth_links(dims, 5030)
     kappas = [KAPPAS[r % 4] for r in range(nrhs)]
     bs = np.stack([synth.gaussian_spinor(lat.Vh, 4000 + r) for r in range(nrhs)])
     ctx = make_ctx(dims, U)
     prm = whmc.cg_params(tol=1e-10, prec=prec, links=whmc.L18 if prec == whmc.F64 else whmc.L12, delta=0.1,
-                         rhs_block=nb, rhs_lanes=lanes)
+                         rhs_block=nb, rhs_lanes=lanes, rhs_order=order)
     x, st = ctx.cg_solve(pack_half(ctx, bs), kappas, prm)
     got = unpack_half(ctx, x, nrhs).reshape(nrhs, lat.Vh, 4, 3)
     iters = [s["iters"] for s in st]

@@ -231,3 +231,19 @@ def test_multi_cg_with_a_zero_rhs_and_sixteen_rhs():
     with pytest.raises(whmc.WhmcError) as e:   # at most 16 right-hand sides
         ctx.cg_solve(pack_half(ctx, np.concatenate([bs, bs[:1]])), kappas + [0.15], whmc.cg_params())
     assert e.value.status == 1   # EARG
+
+
+@pytest.mark.parametrize("kernel,chunk", [(0, 24), (0, 1), (1, 24), (1, 7)])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (4, 8, 16, 16), (4, 12, 16, 16)])
+def test_pair_force_kernels_and_chunks(kernel, chunk, dims):
+    """both pair-force contractions (one thread per link, one per site) with 1 .. 24 pairs per launch,
+    on 30 pairs (kappa^4 filter, n_t = 29), against the oracle"""
+    lat = Lattice(dims)
+    U = synth.haar_links(dims, 2140) if dims[1] == 4 else synth.smooth_links(dims, 2140)
+    phi = synth.gaussian_spinor(lat.Vh, 2141)
+    ctx = make_ctx(dims, U)
+    ctx.set_option(whmc.OPT_FORCE_KERNEL, kernel)
+    ctx.set_option(whmc.OPT_FORCE_CHUNK, chunk)
+    F = ctx.force(pack_half(ctx, phi), 2, 29, 29, 0.156, 5.6, solver=whmc.cg_params(tol=1e-14, check_every=4))
+    ref = hpe.filtered_force(lat, U, phi, 0.156, 2, 29, tol=1e-14)
+    assert rel_err(algebra_to_numpy(ctx, F), ref) < 1e-12
