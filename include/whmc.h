@@ -189,6 +189,18 @@ whmc_status whmc_apply_M(whmc_ctx* ctx, double* out, const double* in, double ka
  * Uses context scratch for the intermediates (allocated on first use). */
 whmc_status whmc_apply_MdagM(whmc_ctx* ctx, double* out, const double* in, const double* kappas, int nrhs, int eo);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): whmc_apply_MdagM without any allocation.  The
+ * intermediates live in a static device buffer of WHMC_NOALLOC_SCRATCH_BYTES that the library holds
+ * on every GPU it runs on until the process ends (its address is looked up in whmc_create), so the
+ * lattice must satisfy V * 192 <= WHMC_NOALLOC_SCRATCH_BYTES (V <= 174762 sites, e.g. 16^3 x 32),
+ * else WHMC_EARG.  All calls on one GPU share that buffer: calls that overlap in time on one GPU
+ * (several streams or contexts) race and give wrong results.  The buffer keeps the last call's
+ * contents; nothing in it needs to start at zero.  Arguments and results as for whmc_apply_MdagM. */
+#define WHMC_NOALLOC_SCRATCH_BYTES (32u << 20)
+whmc_status whmc_apply_MdagM_noalloc(whmc_ctx* ctx, double* out, const double* in, const double* kappas, int nrhs,
+                                     int eo);
+
 /* ------------------------------------------------------------------ solver (Sec. 1, 4)
  * Solve M_oo(kappa_r)^dag M_oo(kappa_r) x_r = b_r (odd-site half fields, FP64 whmc layout) by CG
  * from x_r = 0, until the true FP64 residual |b - A x| / |b| <= tol for every r.

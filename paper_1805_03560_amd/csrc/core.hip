@@ -12,6 +12,29 @@ namespace whmc {
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+// Scratch of whmc_apply_MdagM_noalloc: a file-scope device array, so that the entry point needs no
+// allocation.  Every GPU the library runs on holds its own copy until the process ends.  In host
+// code `scratch` names a host-side stand-in, never the device memory: its device address is taken
+// once per device with hipGetSymbolAddress (scratch_address) and only that address is used.
+constexpr size_t kNoAllocScratch = (size_t)WHMC_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+
+static std::mutex g_scratch_mutex;
+static std::map<int, void*> g_scratch_ptr;   // device ordinal -> device address of `scratch`
+
+// device address of `scratch` on the current device `device` (looked up once per device)
+static whmc_status scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  auto it = g_scratch_ptr.find(device);
+  if (it == g_scratch_ptr.end()) {
+    void* p = nullptr;
+    WHMC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    WHMC_CHECK(p != nullptr, WHMC_EHIP, "hipGetSymbolAddress returned no address for the no-allocation scratch");
+    it = g_scratch_ptr.emplace(device, p).first;
+  }
+  *out = it->second;
+  return WHMC_OK;
+}
 
 whmc_status workspace(whmc_ctx* c, const std::string& name, size_t bytes, void** out) {
   auto it = c->ws.find(name);
@@ -605,6 +628,11 @@ whmc_status whmc_create(whmc_ctx** out, const int dims[4], int device, void* str
     whmc_destroy(c);
     return WHMC_EHIP;
   }
+  // the no-allocation entry point's scratch on this device (device current)
+  if (scratch_address(device, &c->noalloc_scratch) != WHMC_OK) {
+    whmc_destroy(c);
+    return WHMC_EHIP;
+  }
   *out = c;
   return WHMC_OK;
 }
@@ -753,6 +781,30 @@ whmc_status whmc_apply_MdagM(whmc_ctx* c, double* out, const double* in, const d
   for (int r = 0; r < nrhs; ++r)
     WHMC_TRY(apply_MdagM_f64(c, out + (size_t)r * 24 * c->Vh, in + (size_t)r * 24 * c->Vh, kappas[r], (double*)te,
                              (double*)to));
+  return WHMC_OK;
+}
+
+whmc_status whmc_apply_MdagM_noalloc(whmc_ctx* c, double* out, const double* in, const double* kappas, int nrhs,
+                                     int eo) {
+  WHMC_CHECK(c && out && in && kappas && nrhs >= 1, WHMC_EARG, "whmc_apply_MdagM_noalloc: bad argument");
+  WHMC_CHECK(out != in, WHMC_EARG, "whmc_apply_MdagM_noalloc: in and out must differ");
+  WHMC_CHECK(eo == 0 || eo == 1, WHMC_EARG, "whmc_apply_MdagM_noalloc: eo must be 0 (full lattice) or 1 (even/odd)");
+  WHMC_CHECK(c->gauge_loaded, WHMC_ESTATE, "no gauge field loaded");
+  WHMC_CHECK(c->noalloc_scratch, WHMC_ESTATE, "whmc_apply_MdagM_noalloc: no scratch address for this context");
+  // intermediates: even and odd half fields (eo = 1) or one full field (eo = 0), V * 192 bytes either way
+  const size_t hb = (size_t)c->Vh * 192;
+  WHMC_CHECK(2 * hb <= kNoAllocScratch, WHMC_EARG,
+             "whmc_apply_MdagM_noalloc: the lattice needs " + std::to_string(2 * hb) + " bytes of scratch, more than the " +
+                 std::to_string(kNoAllocScratch) + " bytes of the static buffer (V <= " +
+                 std::to_string(kNoAllocScratch / 192) + " sites)");
+  double* t0 = (double*)c->noalloc_scratch;
+  double* t1 = (double*)((char*)c->noalloc_scratch + hb);
+  for (int r = 0; r < nrhs; ++r) {
+    if (eo)
+      WHMC_TRY(apply_MdagM_f64(c, out + (size_t)r * 24 * c->Vh, in + (size_t)r * 24 * c->Vh, kappas[r], t0, t1));
+    else
+      WHMC_TRY(apply_MdagM_full(c, out + (size_t)r * 48 * c->Vh, in + (size_t)r * 48 * c->Vh, kappas[r], t0));
+  }
   return WHMC_OK;
 }
 

@@ -94,6 +94,7 @@ struct whmc_ctx {
   std::map<std::string, std::pair<void*, size_t>> ws;
   std::map<std::string, std::pair<int, double>> tuned;   // autotuned multi-RHS blockings (16 nb + lanes, us)
   whmc::Reduce red{};
+  void* noalloc_scratch = nullptr;   // device address of the static scratch of whmc_apply_MdagM_noalloc
   whmc::CGScalars* scal = nullptr;   // kMaxRhs entries
   whmc::CGScalars* scal_host = nullptr;  // pinned mirror
   double* host_pinned = nullptr;     // small pinned buffer for scalar read-back

@@ -23,6 +23,7 @@ FORCE_PF, FORCE_GAUGE, FORCE_ACCUMULATE = 1, 2, 4
 _STATUS = {0: "OK", 1: "EARG", 2: "EHIP", 3: "ENOCONV", 4: "EUNSUP", 5: "ENOTSU3", 6: "ESTATE", 7: "ENONFINITE"}
 OPT_STREAM_THRESHOLD, OPT_HOP_SCHEDULE, OPT_HOP_CHUNK, OPT_FORCE_KERNEL, OPT_FORCE_CHUNK = 1, 2, 3, 4, 5
 _HALF_BYTES = {F64: 192, F32: 96, F16: 52}
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 class WhmcError(RuntimeError):
@@ -148,6 +149,8 @@ _SIGS = {
                              ctypes.POINTER(CGStats)], ctypes.c_int),
     "whmc_apply_MdagM": ([_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "whmc_apply_M": ([_P, _P, _P, ctypes.c_double, ctypes.c_int], ctypes.c_int),
+    "whmc_apply_MdagM_noalloc": ([_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int],
+                                 ctypes.c_int),
     "whmc_cg_solve_full": ([_P, _P, _P, ctypes.c_double, ctypes.POINTER(CGParams), ctypes.POINTER(CGStats)],
                            ctypes.c_int),
     "whmc_action_full": ([_P, ctypes.POINTER(ctypes.c_double), _P, ctypes.c_double, ctypes.POINTER(CGParams)],
@@ -386,6 +389,14 @@ class Context:
         n = len(kappas)
         out = self.half_spinor(F64, n if eo else 2 * n) if out is None else out
         _check(lib().whmc_apply_MdagM(self._h, _ptr(out), _ptr(inp), (ctypes.c_double * n)(*kappas), n, int(bool(eo))))
+        return out
+
+    def apply_MdagM_noalloc(self, inp, kappas, out, eo=True):
+        """apply_MdagM through the entry point that allocates nothing (static scratch); out must be given"""
+        kappas = [float(k) for k in (kappas if hasattr(kappas, "__len__") else [kappas])]
+        n = len(kappas)
+        _check(lib().whmc_apply_MdagM_noalloc(self._h, _ptr(out), _ptr(inp), (ctypes.c_double * n)(*kappas), n,
+                                              int(bool(eo))))
         return out
 
     def apply_M(self, inp, kappa, dagger=False, out=None):

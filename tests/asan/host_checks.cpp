@@ -146,6 +146,7 @@ static void null_context() {
   EXPECT(whmc_apply_Moo(c, d, d + 1, 0.15, 0) == E);
   EXPECT(whmc_apply_M(c, d, d + 1, 0.15, 0) == E);
   EXPECT(whmc_apply_MdagM(c, d, d + 1, kap, 1, 1) == E);
+  EXPECT(whmc_apply_MdagM_noalloc(c, d, d + 1, kap, 1, 1) == E);
   EXPECT(whmc_cg_solve(c, d, d + 1, kap, 1, &prm, &st) == E);
   EXPECT(whmc_cg_solve_full(c, d, d + 1, 0.15, &prm, &st) == E);
   EXPECT(whmc_bicgstab_solve(c, d, d + 1, 0.15, 0, &prm, &st) == E);
