@@ -33,9 +33,11 @@ DIMS = (64, 32, 32, 32)          # (L_t, L_z, L_y, L_x)
 KAPPA = 0.1575
 # reliable-update thresholds: the iterated residual may fall by 1e-4 (FP32 bulk, ~1e-7 rounding)
 # or 1e-2 (FP16 bulk, ~5e-4 rounding) before r = b - A x is recomputed in FP64
-MIXED_F32 = lambda whmc: whmc.cg_params(tol=1e-10, prec=whmc.F32, links=whmc.L12, delta=1e-4)
-MIXED_F16 = lambda whmc: whmc.cg_params(tol=1e-10, prec=whmc.F16, links=whmc.L12, delta=1e-2)
-BYTES_PER_SITE = {("f64", 18): 1536, ("f64", 12): 1152, ("f32", 18): 768, ("f32", 12): 576, ("f16", 12): 296}
+MIXED_F32 = lambda whmc, links=12: whmc.cg_params(tol=1e-10, prec=whmc.F32, links=links, delta=1e-4)
+MIXED_F16 = lambda whmc, links=12: whmc.cg_params(tol=1e-10, prec=whmc.F16, links=links, delta=1e-2)
+# algorithmic bytes per output site of an even/odd hop: in + out spinor + 8 links
+BYTES_PER_SITE = {("f64", 18): 1536, ("f64", 12): 1152, ("f64", 8): 896, ("f32", 18): 768, ("f32", 12): 576,
+                  ("f32", 8): 448, ("f16", 12): 296, ("f16", 8): 232}
 
 
 def log(*a):
@@ -53,6 +55,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="only the timed apply_H region")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a device copy of 2 GiB (counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--profile-kernel", choices=["hop_f16_l12", "mhop_f64_12rhs", "mhop_f16_12rhs", "pf_force_24"],
+                    help="only run a short workload of one kernel (for rocprofv3 counter passes) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
@@ -73,6 +77,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log("[bench] copy calibration: 3 copies of 2 GiB")
+        return
+    if args.profile_kernel:
+        profile_kernel(args.profile_kernel, whmc, torch, np)
         return
     T, Z, Y, X = DIMS
     V = T * Z * Y * X
@@ -141,6 +148,49 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+def profile_kernel(name, whmc, torch, np):
+    """a few launches of one kernel on its benchmark workload, for counter passes:
+    hop_f16_l12: the chained FP16 even/odd pair (12-real links) on 32^3 x 64;
+    mhop_f64_12rhs / mhop_f16_12rhs: the multi-RHS hop for 12 right-hand sides on 24^3 x 48 with the
+    autotuned blocking; pf_force_24: the pair force of 24 (X, Y) pairs (kappa^4 filter, n_t = 23)
+    on 32^3 x 64."""
+    from paper_1805_03560_amd import synth
+    dev = torch.device("cuda", 0)
+    if name.startswith("mhop"):
+        dims = (48, 24, 24, 24)
+        U = synth.smooth_links(dims, 4000, threads=min(16, os.cpu_count() or 1))
+    else:
+        dims = DIMS
+        U = synth.smooth_links(dims, 3000, width=0.3, threads=min(16, os.cpu_count() or 1))
+    ctx = whmc.Context(dims, device=0)
+    ctx.load_gauge(torch.from_numpy(U).to(dev), unitarity_tol=1e-11)
+    del U
+    Vh = ctx.Vh
+    if name == "hop_f16_l12":
+        x = ctx.convert_spinor(ctx.pack_spinor(torch.from_numpy(synth.gaussian_spinor(Vh, 3001)).to(dev), 1),
+                               whmc.F64, whmc.F16)
+        us = chained_pair_us(ctx, torch, ctx.stream, whmc.F16, whmc.L12, x, steps=5, warmup=2)
+        info = {"us_per_hop": us}
+    elif name.startswith("mhop"):
+        n = 12
+        prec, links = (whmc.F64, whmc.L18) if "f64" in name else (whmc.F16, whmc.L12)
+        b = ctx.pack_spinor(torch.from_numpy(np.stack([synth.gaussian_spinor(Vh, 4100 + r) for r in range(n)]))
+                            .to(dev), 0)
+        bp = b if prec == whmc.F64 else ctx.convert_spinor(b, whmc.F64, prec, n)
+        nb, lanes, order, _ = ctx.autotune(prec, links, n)
+        o = ctx.half_spinor(prec, n)
+        for _ in range(3):
+            ctx.apply_H_multi(bp, 0, n, prec=prec, links=links, rhs_block=nb, rhs_lanes=lanes, rhs_order=order, out=o)
+        info = {"blocking": [nb, lanes, order]}
+    else:
+        phi = ctx.pack_spinor(torch.from_numpy(synth.gaussian_spinor(Vh, 3003)).to(dev), 0)
+        ctx.force(phi, 2, 23, 29, KAPPA, 5.6, solver=whmc.cg_params(tol=1e-10))
+        info = {"pairs": 24}
+    torch.cuda.synchronize()
+    ctx.close()
+    print(json.dumps({"profile_kernel": name, **info}), flush=True)
+
+
 def measured_traffic(bytes_per_launch):
     """HBM bytes per launch from the committed rocprofv3 counter summary of this kernel, if its
     recorded source digest still matches the stencil sources (else null)."""
@@ -199,8 +249,11 @@ def extras(ctx, whmc, torch, np, stream, Vh):
     t = {}
     for name, prm in [("fp64", whmc.cg_params(tol=1e-10)),
                       ("fp64_l12", whmc.cg_params(tol=1e-10, links=whmc.L12)),
+                      ("fp64_l8", whmc.cg_params(tol=1e-10, links=whmc.L8)),
                       ("mixed_f32_l12", MIXED_F32(whmc)),
-                      ("mixed_f16_l12", MIXED_F16(whmc))]:
+                      ("mixed_f32_l8", MIXED_F32(whmc, whmc.L8)),
+                      ("mixed_f16_l12", MIXED_F16(whmc)),
+                      ("mixed_f16_l8", MIXED_F16(whmc, whmc.L8))]:
         ctx.cg_solve(b, [KAPPA], prm)      # warm-up of this path
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -218,8 +271,9 @@ def extras(ctx, whmc, torch, np, stream, Vh):
             cgr[name]["rel_err_vs_oracle"] = err_vs_golden(ctx, x, golden, np)["rel_err_sampled"]
         log(f"[bench] CG {name}: {ms:.1f} ms, {s['iters']} iters, res {s['true_residual']:.2e}, err {err:.2e}, "
             f"vs oracle {cgr[name].get('rel_err_vs_oracle')}")
-    for name in ("fp64_l12", "mixed_f32_l12", "mixed_f16_l12"):
-        cgr[name]["speedup_vs_fp64"] = round(t["fp64"] / t[name], 3)
+    for name in t:
+        if name != "fp64":
+            cgr[name]["speedup_vs_fp64"] = round(t["fp64"] / t[name], 3)
     if golden is not None:
         cgr["oracle_solution"] = {"file": "tests/golden/cg_32x64_kappa0.1575.npz", "sites": int(len(golden["sites"])),
                                   "tol": golden["meta"]["cg_tol"], "iterations": golden["meta"]["iterations"]}
@@ -273,8 +327,9 @@ def hop_formats(ctx, whmc, torch, stream, Vh):
     from paper_1805_03560_amd import synth
     fmt = {}
     x64 = ctx.pack_spinor(torch.from_numpy(synth.gaussian_spinor(Vh, 3002)).to(ctx.device), 1)
-    for (p, pn), links in [((whmc.F64, "f64"), 18), ((whmc.F64, "f64"), 12), ((whmc.F32, "f32"), 18),
-                           ((whmc.F32, "f32"), 12), ((whmc.F16, "f16"), 12)]:
+    for (p, pn), links in [((whmc.F64, "f64"), 18), ((whmc.F64, "f64"), 12), ((whmc.F64, "f64"), 8),
+                           ((whmc.F32, "f32"), 18), ((whmc.F32, "f32"), 12), ((whmc.F32, "f32"), 8),
+                           ((whmc.F16, "f16"), 12), ((whmc.F16, "f16"), 8)]:
         xin = x64.clone() if p == whmc.F64 else ctx.convert_spinor(x64, whmc.F64, p)
         us = chained_pair_us(ctx, torch, stream, p, links, xin)
         gbs = BYTES_PER_SITE[(pn, links)] * Vh / (us * 1e-6) / 1e9
