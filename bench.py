@@ -101,10 +101,10 @@ def main():
         ctx.apply_H(t_e, 1, out=psi[(k + 1) & 1])        # psi_o' = H_oe t_e
 
     # setup: the autotuner picks the workgroup schedule of the stencil kernels (time-slice ranges per
-    # XCD, or time slabs worked through in chunks of a given size) by timing the same hop pair
-    sched, chunk, tuned_us = ctx.autotune_hop()
-    log(f"[bench] stencil schedule: {'slice ranges' if sched == 0 else f'time slabs, chunks of {chunk} blocks'} "
-        f"({tuned_us:.1f} us per hop while tuning)")
+    # XCD, or time slabs worked through in chunks of a given size) and the occupancy cap (none, or two
+    # workgroups per compute unit) by timing the same hop pair
+    tuned = tune_stencil(ctx, whmc)
+    log(f"[bench] stencil schedule: {tuned}")
 
     # ------------------------------------------------------------ timed region: apply_H FP64
     for k in range(args.warmup):
@@ -136,7 +136,7 @@ def main():
                    "lattice_t_z_y_x": list(DIMS), "sites": V, "kappa": KAPPA},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(bytes_per_launch)},
-        "stencil_schedule": {"schedule": sched, "chunk_blocks": chunk, "tuned_us_per_hop": round(tuned_us, 1)},
+        "stencil_schedule": tuned,
     }
 
     if not args.no_extras:
@@ -164,6 +164,7 @@ def profile_kernel(name, whmc, torch, np):
         U = synth.smooth_links(dims, 3000, width=0.3, threads=min(16, os.cpu_count() or 1))
     ctx = whmc.Context(dims, device=0)
     ctx.load_gauge(torch.from_numpy(U).to(dev), unitarity_tol=1e-11)
+    tune_stencil(ctx, whmc)
     del U
     Vh = ctx.Vh
     if name == "hop_f16_l12":
@@ -191,6 +192,13 @@ def profile_kernel(name, whmc, torch, np):
     print(json.dumps({"profile_kernel": name, **info}), flush=True)
 
 
+def tune_stencil(ctx, whmc):
+    """autotune the single-RHS stencil schedule and occupancy cap of a context; returns the choice"""
+    sched, chunk, us = ctx.autotune_hop()
+    return {"schedule": "slice ranges" if sched == 0 else "time slabs", "chunk_blocks": chunk,
+            "wg_per_cu": ctx.get_option(whmc.OPT_HOP_WG_PER_CU) or None, "tuned_us_per_hop": round(us, 1)}
+
+
 def measured_traffic(bytes_per_launch):
     """HBM bytes per launch from the committed rocprofv3 counter summary of this kernel, if its
     recorded source digest still matches the stencil sources (else null)."""
@@ -198,17 +206,10 @@ def measured_traffic(bytes_per_launch):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
+    from paper_1805_03560_amd.profsum import source_digest
     if rec.get("source_digest") != source_digest():
         return None
     return rec.get("bytes_per_launch")
-
-
-def source_digest():
-    import hashlib
-    h = hashlib.sha256()
-    for f in ("device.h", "stencil.h", "core.hip"):
-        h.update(open(os.path.join(ROOT, "paper_1805_03560_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
 
 
 def time_events(fn, stream, torch, reps=1):
@@ -368,7 +369,7 @@ def cg_16x32(whmc, torch):
     ctx = whmc.Context(dims, device=0)
     ctx.load_gauge(torch.from_numpy(U).to(ctx.device), unitarity_tol=1e-11)
     b = ctx.pack_spinor(torch.from_numpy(synth.gaussian_spinor(ctx.Vh, 2001)).to(ctx.device), 0)
-    res = {}
+    res = {"stencil_schedule": tune_stencil(ctx, whmc)}
     for kappa in (0.156, 0.1575):
         prm = whmc.cg_params(tol=1e-10)
         ctx.cg_solve(b, [kappa], prm)
@@ -389,6 +390,7 @@ def bicgstab_vs_cgne(whmc, torch):
     U = synth.smooth_links(DIMS, 3005, width=0.8, threads=min(16, os.cpu_count() or 1))
     ctx = whmc.Context(DIMS, device=0)
     ctx.load_gauge(torch.from_numpy(U).to(ctx.device), unitarity_tol=1e-11)
+    tune_stencil(ctx, whmc)
     del U
     stream = ctx.stream
     Vh = ctx.Vh
@@ -417,7 +419,7 @@ def multi_rhs(whmc, torch, stream):
     ctx.load_gauge(torch.from_numpy(U).to(ctx.device), unitarity_tol=1e-11)
     del U
     kp = [0.150, 0.153, 0.156, 0.1575]
-    res = {}
+    res = {"stencil_schedule": tune_stencil(ctx, whmc)}
     for nrhs in (4, 8, 12):
         import numpy as np
         bs = np.stack([synth.gaussian_spinor(Vh, 4100 + r) for r in range(nrhs)])
@@ -552,6 +554,7 @@ def widened_16x32(whmc, torch):
     U = synth.smooth_links(dims, 3200, width=0.55)
     ctx = whmc.Context(dims, device=0)
     ctx.load_gauge(torch.from_numpy(U).to(ctx.device), unitarity_tol=1e-11)
+    tune_stencil(ctx, whmc)
     U0 = ctx.export_gauge()
     stream = ctx.stream
     Vh = ctx.Vh

@@ -103,18 +103,27 @@ whmc_status whmc_set_stream(whmc_ctx* ctx, void* stream);
  *   WHMC_OPT_FORCE_KERNEL      pseudo-fermion force contraction: 0 = one thread per link (default),
  *                              1 = one thread per site and its four links.
  *   WHMC_OPT_FORCE_CHUNK       (X, Y) pairs summed per launch of that contraction, 1 .. 24 (default
- *                              24); later launches accumulate.  Results agree to rounding. */
+ *                              24); later launches accumulate.  Results agree to rounding.
+ *   WHMC_OPT_HOP_WG_PER_CU     occupancy cap of those kernels that work on FP64 spinors: 0 = none
+ *                              (default), 2 .. 8 = at most that many 128-thread workgroups per
+ *                              compute unit (each reserves LDS it does not use).  Fewer sites in
+ *                              flight keep their neighbour spinors in the L2 of their XCD.  The
+ *                              FP32 / FP16 kernels are never capped.  EARG if the device's LDS
+ *                              limits do not allow the value.  Results do not depend on it. */
 #define WHMC_OPT_HOP_SCHEDULE 2
 #define WHMC_OPT_HOP_CHUNK 3
 #define WHMC_OPT_FORCE_KERNEL 4
 #define WHMC_OPT_FORCE_CHUNK 5
+#define WHMC_OPT_HOP_WG_PER_CU 6
 whmc_status whmc_set_option(whmc_ctx* ctx, int option, long long value);
 whmc_status whmc_get_option(const whmc_ctx* ctx, int option, long long* value);
 
 /* Autotuner of the single-RHS stencil schedule: times the FP64 even/odd hop pair (H_eo then H_oe,
- * 18-real links) for schedule 0 and for schedule 1 with chunks of 1/16 .. 1/2 of a time slice, and
- * keeps the fastest in the context (WHMC_OPT_HOP_SCHEDULE / WHMC_OPT_HOP_CHUNK).  Outputs may be
- * NULL; us receives the time per hop in microseconds.  Uses context scratch of two half fields. */
+ * 18-real links) for schedule 0 and for schedule 1 with chunks of 1/16 .. 1/2 of a time slice, each
+ * without and with a cap of 2 workgroups per compute unit, and keeps the fastest in the context
+ * (WHMC_OPT_HOP_SCHEDULE / WHMC_OPT_HOP_CHUNK / WHMC_OPT_HOP_WG_PER_CU, read back with
+ * whmc_get_option).  Outputs may be NULL; us receives the time per hop in microseconds.  Uses context
+ * scratch of two half fields.  On an error the schedule and cap are left as they were. */
 whmc_status whmc_autotune_hop(whmc_ctx* ctx, int* schedule, int* chunk, double* us);
 
 /* Bytes of one field of the given kind in the whmc layout:

@@ -250,12 +250,14 @@ static void enqueue_bs(whmc_ctx* c, const Lnk& L, SpinorF64 x, SpinorF64 r, Spin
   const Reduce red = c->red;
   for (int it = 0; it < n; ++it) {
     TraceRange tr("whmc bicgstab iteration");
-    hipLaunchKernelGGL((k_bs_hop<DAG, Lnk>), gs, blk, 0, c->stream, c->g, L, p, te, sc);
-    hipLaunchKernelGGL((k_bs_mv<DAG, 0, Lnk>), gs, blk, 0, c->stream, c->g, L, te, p, v, rhat, k2, sc, red, ns);
+    hipLaunchKernelGGL((k_bs_hop<DAG, Lnk>), gs, blk, c->stencil_lds, c->stream, c->g, L, p, te, sc);
+    hipLaunchKernelGGL((k_bs_mv<DAG, 0, Lnk>), gs, blk, c->stencil_lds, c->stream, c->g, L, te, p, v, rhat, k2, sc,
+                       red, ns);
     hipLaunchKernelGGL(k_bs_fin<0>, dim3(1), dim3(256), 0, c->stream, sc, red.partials, ns);
     hipLaunchKernelGGL(k_bs_s, gv, blk, 0, c->stream, c->Vh, r, v, s, sc);
-    hipLaunchKernelGGL((k_bs_hop<DAG, Lnk>), gs, blk, 0, c->stream, c->g, L, s, te, sc);
-    hipLaunchKernelGGL((k_bs_mv<DAG, 1, Lnk>), gs, blk, 0, c->stream, c->g, L, te, s, t, s, k2, sc, red, ns);
+    hipLaunchKernelGGL((k_bs_hop<DAG, Lnk>), gs, blk, c->stencil_lds, c->stream, c->g, L, s, te, sc);
+    hipLaunchKernelGGL((k_bs_mv<DAG, 1, Lnk>), gs, blk, c->stencil_lds, c->stream, c->g, L, te, s, t, s, k2, sc,
+                       red, ns);
     hipLaunchKernelGGL(k_bs_fin<1>, dim3(1), dim3(256), 0, c->stream, sc, red.partials, ns);
     hipLaunchKernelGGL(k_bs_update, gv, blk, 0, c->stream, c->Vh, x, p, s, t, r, rhat, sc, red, nv);
     hipLaunchKernelGGL(k_bs_fin_rho, dim3(1), dim3(256), 0, c->stream, sc, red.partials, nv);

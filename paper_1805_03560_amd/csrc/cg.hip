@@ -19,6 +19,7 @@
 // FP64 operator, restores p's orthogonality to r and resumes.
 #include <chrono>
 #include <cmath>
+#include <type_traits>
 
 #include "internal.h"
 #include "stencil.h"
@@ -275,14 +276,16 @@ static SpinorF16 s16(void* p, int Vh) { return SpinorF16{(uint4*)p, (float*)((ui
 template <class Lnk, class S, class SR, bool MIXED>
 static whmc_status enqueue_iters(whmc_ctx* c, const Lnk& L, S p, S t, S u, S v, SR r, SR x, double kappa, int n) {
   const dim3 grid(c->site_blocks()), block(kBlock);
+  // occupancy cap of the FP64 stencil kernels (the low-precision ones need every wave)
+  const unsigned lds = std::is_same<S, SpinorF64>::value ? c->stencil_lds : 0u;
   const double k2 = kappa * kappa;
   for (int it = 0; it < n; ++it) {
     TraceRange tr(MIXED ? "whmc cg iteration (mixed)" : "whmc cg iteration");
-    hipLaunchKernelGGL((k_cg1<Lnk, S>), grid, block, 0, c->stream, c->g, L, p, t, c->scal);
-    hipLaunchKernelGGL((k_cg2<Lnk, S>), grid, block, 0, c->stream, c->g, L, t, p, u, k2, c->scal, c->red);
+    hipLaunchKernelGGL((k_cg1<Lnk, S>), grid, block, lds, c->stream, c->g, L, p, t, c->scal);
+    hipLaunchKernelGGL((k_cg2<Lnk, S>), grid, block, lds, c->stream, c->g, L, t, p, u, k2, c->scal, c->red);
     hipLaunchKernelGGL(k_cg2_fin, dim3(1), dim3(256), 0, c->stream, c->scal, c->red.partials, (int)grid.x);
-    hipLaunchKernelGGL((k_cg3<Lnk, S>), grid, block, 0, c->stream, c->g, L, u, v, c->scal);
-    hipLaunchKernelGGL((k_cg4<Lnk, S, SR, MIXED>), grid, block, 0, c->stream, c->g, L, v, u, p, r, x, k2, c->scal,
+    hipLaunchKernelGGL((k_cg3<Lnk, S>), grid, block, lds, c->stream, c->g, L, u, v, c->scal);
+    hipLaunchKernelGGL((k_cg4<Lnk, S, SR, MIXED>), grid, block, lds, c->stream, c->g, L, v, u, p, r, x, k2, c->scal,
                        c->red);
     hipLaunchKernelGGL(k_cg4_fin<MIXED>, dim3(1), dim3(256), 0, c->stream, c->scal, c->red.partials, (int)grid.x);
     hipLaunchKernelGGL((k_cg5<S, SR>), grid, block, 0, c->stream, c->Vh, p, r, c->scal);

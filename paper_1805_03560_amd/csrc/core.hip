@@ -86,7 +86,10 @@ template <class Lnk, class S>
 static whmc_status launch_hop(whmc_ctx* c, const Lnk& L, int par, int dag, S in, S x, S out, bool xpay, double a,
                               double b, double* norm_out, bool nts) {
   dim3 grid(c->site_blocks()), block(kBlock);
-#define WHMC_L(D, XP, N, NS) hipLaunchKernelGGL((k_hop<D, XP, N, NS, Lnk, S, S, S>), grid, block, 0, c->stream, c->g, \
+  // the occupancy cap applies to FP64 spinors only (the low-precision kernels need every wave)
+  const unsigned lds = std::is_same<S, SpinorF64>::value ? c->stencil_lds : 0u;
+#define WHMC_L(D, XP, N, NS) hipLaunchKernelGGL((k_hop<D, XP, N, NS, Lnk, S, S, S>), grid, block, lds, \
+                                                c->stream, c->g, \
                                                 par, L, in, x, out, a, b, c->red, norm_out)
   const bool norm = norm_out != nullptr;
   if (xpay) {
@@ -611,6 +614,10 @@ whmc_status whmc_create(whmc_ctx** out, const int dims[4], int device, void* str
   }
   c->device = device;
   c->stream = (hipStream_t)stream;
+  if (hipDeviceGetAttribute(&c->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) !=
+          hipSuccess ||
+      hipDeviceGetAttribute(&c->lds_per_wg, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
+    c->lds_per_cu = c->lds_per_wg = 0;   // no occupancy cap on this device
   const size_t nlinks = (size_t)8 * c->Vh;
   hipError_t e = hipMalloc(&c->U18, nlinks * 9 * sizeof(double2));
   // partial sums: up to 8 rows per rhs (multi-RHS sub-blocks) of stencil_blocks() slots each
@@ -819,33 +826,47 @@ whmc_status whmc_autotune_hop(whmc_ctx* c, int* schedule, int* chunk, double* us
   WHMC_TRY(workspace(c, "tune_hop_x", hb, &x));
   WHMC_TRY(workspace(c, "tune_hop_t", hb, &t));
   WHMC_TRY(zero_bytes(c, x, hb));
-  std::vector<std::pair<int, int>> cand{{0, c->hop_chunk}};
+  // candidates: (schedule, chunk, workgroups per CU)
+  struct Cand {
+    int sched, chunk, cap;
+  };
+  std::vector<std::pair<int, int>> sc{{0, c->hop_chunk}};
   if (c->g.nbs > 0 && c->g.L[0] % 8 == 0)
     for (int d : {16, 8, 4, 2}) {
       const int q = (c->g.nbs + d - 1) / d;
       bool seen = false;
-      for (auto& p : cand) seen |= (p.first == 1 && p.second == q);
-      if (!seen) cand.push_back({1, q});
+      for (auto& p : sc) seen |= (p.first == 1 && p.second == q);
+      if (!seen) sc.push_back({1, q});
     }
+  const int saved_cap = c->hop_wg_per_cu;
+  std::vector<Cand> cand;
+  for (auto& p : sc)
+    for (int cap : {0, 2})
+      if (c->set_wg_cap(cap)) cand.push_back({p.first, p.second, cap});
   hipEvent_t e0, e1;
   WHMC_HIP(hipEventCreate(&e0));
   WHMC_HIP(hipEventCreate(&e1));
   const Geom saved = c->g;
   double best = 1e30;
-  std::pair<int, int> pick = cand[0];
+  Cand pick = cand[0];
+  whmc_status rc = WHMC_OK;
   for (const auto& cd : cand) {
-    c->set_schedule(cd.first, cd.second);
+    c->set_schedule(cd.sched, cd.chunk);
+    c->set_wg_cap(cd.cap);
     auto pair = [&]() -> whmc_status {
       WHMC_TRY(hop(c, WHMC_F64, WHMC_L18, 0, 0, t, x, nullptr, 0.0, 1.0, nullptr));
       return hop(c, WHMC_F64, WHMC_L18, 1, 0, x, t, nullptr, 0.0, 1.0, nullptr);
     };
-    WHMC_TRY(pair());
-    WHMC_HIP(hipEventRecord(e0, c->stream));
-    for (int rep = 0; rep < 5; ++rep) WHMC_TRY(pair());
-    WHMC_HIP(hipEventRecord(e1, c->stream));
-    WHMC_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
-    WHMC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    rc = pair();
+    for (int rep = 0; rep < 5 && rc == WHMC_OK; ++rep) {
+      if (rep == 0 && hipEventRecord(e0, c->stream) != hipSuccess) rc = WHMC_EHIP;
+      if (rc == WHMC_OK) rc = pair();
+    }
+    if (rc == WHMC_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = WHMC_EHIP;
+    if (rc != WHMC_OK) break;
     const double per_hop = ms * 1e3 / 10.0;
     if (per_hop < best) {
       best = per_hop;
@@ -855,8 +876,13 @@ whmc_status whmc_autotune_hop(whmc_ctx* c, int* schedule, int* chunk, double* us
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->g = saved;
-  c->set_schedule(pick.first, pick.second);
-  if (pick.first == 1) c->hop_chunk = pick.second;
+  if (rc != WHMC_OK) {
+    c->set_wg_cap(saved_cap);
+    return rc;
+  }
+  c->set_schedule(pick.sched, pick.chunk);
+  if (pick.sched == 1) c->hop_chunk = pick.chunk;
+  c->set_wg_cap(pick.cap);
   if (schedule) *schedule = c->g.sched;
   if (chunk) *chunk = c->hop_chunk;
   if (us) *us = best;
@@ -884,6 +910,11 @@ whmc_status whmc_set_option(whmc_ctx* c, int option, long long value) {
       WHMC_CHECK(value >= 1 && value <= 24, WHMC_EARG, "whmc_set_option: pairs per force launch must be 1 .. 24");
       c->force_chunk = (int)value;
       return WHMC_OK;
+    case WHMC_OPT_HOP_WG_PER_CU:
+      WHMC_CHECK(value == 0 || (value >= 2 && value <= 8 && c->set_wg_cap((int)value)), WHMC_EARG,
+                 "whmc_set_option: workgroups per compute unit must be 0 (no cap) or 2 .. 8");
+      if (value == 0) c->set_wg_cap(0);
+      return WHMC_OK;
     case WHMC_OPT_HOP_SCHEDULE:
       WHMC_CHECK(value == 0 || value == 1, WHMC_EARG, "whmc_set_option: the schedule must be 0 or 1");
       WHMC_CHECK(c->set_schedule((int)value, c->hop_chunk), WHMC_EARG,
@@ -901,6 +932,7 @@ whmc_status whmc_get_option(const whmc_ctx* c, int option, long long* value) {
   switch (option) {
     case WHMC_OPT_STREAM_THRESHOLD: *value = c->stream_threshold; return WHMC_OK;
     case WHMC_OPT_HOP_SCHEDULE: *value = c->g.sched; return WHMC_OK;
+    case WHMC_OPT_HOP_WG_PER_CU: *value = c->hop_wg_per_cu; return WHMC_OK;
     case WHMC_OPT_HOP_CHUNK: *value = c->hop_chunk; return WHMC_OK;
     case WHMC_OPT_FORCE_KERNEL: *value = c->force_kernel; return WHMC_OK;
     case WHMC_OPT_FORCE_CHUNK: *value = c->force_chunk; return WHMC_OK;

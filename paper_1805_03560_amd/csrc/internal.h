@@ -105,6 +105,13 @@ struct whmc_ctx {
   int hop_chunk = 0;   // tq of the time-slab schedule (WHMC_OPT_HOP_CHUNK)
   int force_kernel = 0;   // pair-force kernel: 0 link-parallel, 1 site-parallel (WHMC_OPT_FORCE_KERNEL)
   int force_chunk = 24;   // (X, Y) pairs per launch of the pair-force kernel (WHMC_OPT_FORCE_CHUNK)
+  // occupancy cap of the single-RHS stencil kernels (WHMC_OPT_HOP_WG_PER_CU): each workgroup
+  // reserves stencil_lds bytes of LDS it does not use, so that at most hop_wg_per_cu workgroups fit
+  // on a compute unit (0 = no cap, stencil_lds = 0).  Fewer sites in flight per XCD keep the
+  // neighbour spinors of the sites in flight inside that XCD's L2.
+  int hop_wg_per_cu = 0;
+  unsigned stencil_lds = 0;
+  int lds_per_cu = 0, lds_per_wg = 0;   // device limits, read at creation
   bool stream_links(int prec, int links) const {
     if (stream_threshold < 0) return false;
     const long long per = links == 8 ? (prec == 0 ? 64 : prec == 1 ? 32 : 16)
@@ -117,6 +124,22 @@ struct whmc_ctx {
   int stencil_blocks() const { return g.xq ? 8 * g.xq * g.L[0] : num_blocks(); }
   // grid of the single-RHS stencil kernels (site_block), for the schedule in g.sched
   int site_blocks() const { return g.sched == 1 ? 8 * g.tx * g.nch * g.tq : stencil_blocks(); }
+  // at most k workgroups per compute unit for the single-RHS stencil kernels (k = 0: no cap; else
+  // 2 <= k <= 8): reserve the smallest multiple of 2 KiB above lds_per_cu / (k + 1) bytes, so that
+  // k workgroups fit and k + 1 do not (false, unchanged, if the device cannot do it)
+  bool set_wg_cap(int k) {
+    if (k == 0) {
+      hop_wg_per_cu = 0;
+      stencil_lds = 0;
+      return true;
+    }
+    if (k < 2 || k > 8 || lds_per_cu <= 0) return false;
+    const long long b = ((long long)lds_per_cu / (k + 1) + 1 + 2047) / 2048 * 2048;
+    if (b * k > lds_per_cu || b * (k + 1) <= lds_per_cu || b > lds_per_wg) return false;
+    hop_wg_per_cu = k;
+    stencil_lds = (unsigned)b;
+    return true;
+  }
   // time-slab schedule with chunks of tq blocks, if the lattice allows it (else false, unchanged)
   bool set_schedule(int sched, int tq) {
     if (sched == 0) { g.sched = 0; return true; }

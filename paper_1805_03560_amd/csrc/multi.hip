@@ -495,13 +495,21 @@ static void launch_mhop(whmc_ctx* c, int par, int dag, int nrhs, int order, cons
     hipLaunchKernelGGL((k_mhop<0, NB, R, Lnk, S>), grid, block, 0, c->stream, c->g, par, nrhs, G, order, L, in, out);
 }
 
-// dispatch on precision / link format / cache policy; f(L, S-maker) is called with the typed link
-// accessor and a function turning a device pointer into the spinor accessor of that precision.
+// Links are streamed past the caches (non-temporal loads, for link arrays above the stream
+// threshold) only where one launch reads each link once: with block-major order and several rhs
+// groups, the groups of a site block run back to back and re-read the block's links from L2.
+static bool stream_multi(const whmc_ctx* c, int prec, int links, int nrhs, const Blocking& b) {
+  const int G = (nrhs + b.nb * b.lanes - 1) / (b.nb * b.lanes);
+  return c->stream_links(prec, links) && (G == 1 || b.order == 1);
+}
+
+// dispatch on precision / link format / cache policy (nt: non-temporal link loads); f(L, S-maker)
+// is called with the typed link accessor and a function turning a device pointer into the spinor
+// accessor of that precision.
 template <class F>
-static whmc_status with_format(whmc_ctx* c, int prec, int links, F&& f) {
+static whmc_status with_format(whmc_ctx* c, int prec, int links, bool nt, F&& f) {
   WHMC_TRY(ensure_links(c, prec, links));
   const int Vh = c->Vh;
-  const bool nt = c->stream_links(prec, links);
   if (prec == WHMC_F64 && links == WHMC_L18) {
     if (nt) return f(LinkF64_18T<true>{c->U18, Vh}, h64);
     return f(LinkF64_18T<false>{c->U18, Vh}, h64);
@@ -524,7 +532,7 @@ static whmc_status with_format(whmc_ctx* c, int prec, int links, F&& f) {
 
 static whmc_status mhop(whmc_ctx* c, int prec, int links, int par, int dag, int nrhs, Blocking b, void* out,
                         const void* in) {
-  WHMC_TRY(with_format(c, prec, links, [&](auto L, auto mk) {
+  WHMC_TRY(with_format(c, prec, links, stream_multi(c, prec, links, nrhs, b), [&](auto L, auto mk) {
     return with_blocking<decltype(L)>(b, [&](auto nb, auto lanes) {
       launch_mhop<decltype(nb)::value, decltype(lanes)::value>(c, par, dag, nrhs, b.order, L, mk((void*)in, c->Vh),
                                                                 mk(out, c->Vh));
@@ -743,7 +751,8 @@ static whmc_status residual_multi(whmc_ctx* c, unsigned mask, int nrhs, const do
       return WHMC_OK;
     });
   };
-  if (c->stream_links(WHMC_F64, WHMC_L18)) WHMC_TRY(run(LinkF64_18T<true>{c->U18, Vh}));
+  const Blocking b1{1, bk.lanes, bk.order};   // the residual kernels hold one rhs per thread
+  if (stream_multi(c, WHMC_F64, WHMC_L18, nrhs, b1)) WHMC_TRY(run(LinkF64_18T<true>{c->U18, Vh}));
   else WHMC_TRY(run(LinkF64_18T<false>{c->U18, Vh}));
   WHMC_HIP(hipGetLastError());
   return WHMC_OK;
@@ -825,7 +834,7 @@ whmc_status cg_solve_multi(whmc_ctx* c, double* x, const double* b, const double
   for (int pass = 0; pass < 4 && !all; ++pass) {
     int max_iter_seen = 0;
     while (true) {
-      WHMC_TRY(with_format(c, prec, links, [&](auto L, auto mk) {
+      WHMC_TRY(with_format(c, prec, links, stream_multi(c, prec, links, nrhs, bk), [&](auto L, auto mk) {
         return with_blocking<decltype(L)>(bk, [&](auto nbc, auto lanes) {
           constexpr int NB = decltype(nbc)::value, R = decltype(lanes)::value;
           // FP64 links run the plain FP64 CG, low-precision links the mixed one
@@ -871,7 +880,7 @@ whmc_status cg_solve_multi(whmc_ctx* c, double* x, const double* b, const double
           hipLaunchKernelGGL(k_mresume, dim3(1), dim3(64), 0, c->stream, c->scal, r, rr_dev + r, ok);
           if (!ok) {
             const dim3 gr(c->num_blocks());
-            WHMC_TRY(with_format(c, prec, links, [&](auto L, auto mk) {
+            WHMC_TRY(with_format(c, prec, links, false, [&](auto L, auto mk) {
               (void)L;
               hipLaunchKernelGGL((k_mdot_rp<decltype(mk(pr, Vh)), SpinorF32>), gr, dim3(kBlock), 0, c->stream, Vh,
                                  mk(pr, Vh), h32(rsr, Vh), c->red, c->red.result + 6);

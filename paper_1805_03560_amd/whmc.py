@@ -21,7 +21,7 @@ L8, L12, L18 = 8, 12, 18
 LEAPFROG, OMELYAN = 0, 1
 FORCE_PF, FORCE_GAUGE, FORCE_ACCUMULATE = 1, 2, 4
 _STATUS = {0: "OK", 1: "EARG", 2: "EHIP", 3: "ENOCONV", 4: "EUNSUP", 5: "ENOTSU3", 6: "ESTATE", 7: "ENONFINITE"}
-OPT_STREAM_THRESHOLD, OPT_HOP_SCHEDULE, OPT_HOP_CHUNK, OPT_FORCE_KERNEL, OPT_FORCE_CHUNK = 1, 2, 3, 4, 5
+OPT_STREAM_THRESHOLD, OPT_HOP_SCHEDULE, OPT_HOP_CHUNK, OPT_FORCE_KERNEL, OPT_FORCE_CHUNK, OPT_HOP_WG_PER_CU = 1, 2, 3, 4, 5, 6
 _HALF_BYTES = {F64: 192, F32: 96, F16: 52}
 NOALLOC_SCRATCH_BYTES = 32 << 20
 

@@ -1,6 +1,8 @@
-"""The single-RHS stencil schedules (WHMC_OPT_HOP_SCHEDULE) and their autotuner: every schedule and
-chunk gives the same hop bit for bit (a site's arithmetic does not depend on which workgroup does
-it), solvers on the time-slab schedule match the oracle, and the tuner keeps a valid choice."""
+"""The single-RHS stencil schedules (WHMC_OPT_HOP_SCHEDULE), the occupancy cap
+(WHMC_OPT_HOP_WG_PER_CU) and their autotuner: every schedule, chunk and cap gives the same hop bit
+for bit (a site's arithmetic does not depend on which workgroup does it or how many share a compute
+unit), solvers on the time-slab schedule with a cap match the oracle, and the tuner keeps a valid
+choice."""
 import numpy as np
 import pytest
 
@@ -27,7 +29,12 @@ def test_schedules_give_identical_hops(dims):
     ref = dirac.apply_Hblock(lat, U, x, 0)
     base = ctx.apply_H(xb, 0).clone()
     assert rel_err(unpack_half(ctx, base), ref) < 1e-12
-    for chunk in (1, 3, 8):   # 3: the last chunk of a slice is ragged (padding workgroups)
+    for cap in (2, 4):
+        ctx.set_option(whmc.OPT_HOP_WG_PER_CU, cap)
+        assert ctx.get_option(whmc.OPT_HOP_WG_PER_CU) == cap
+        assert bool((ctx.apply_H(xb, 0) == base).all())
+    for chunk, cap in [(1, 0), (3, 2), (8, 8)]:   # 3: the last chunk of a slice is ragged (padding workgroups)
+        ctx.set_option(whmc.OPT_HOP_WG_PER_CU, cap)
         ctx.set_option(whmc.OPT_HOP_CHUNK, chunk)
         ctx.set_option(whmc.OPT_HOP_SCHEDULE, 1)
         assert ctx.get_option(whmc.OPT_HOP_SCHEDULE) == 1 and ctx.get_option(whmc.OPT_HOP_CHUNK) == chunk
@@ -48,6 +55,7 @@ def test_solvers_on_the_slab_schedule(dims):
     ctx = make_ctx(dims, U)
     ctx.set_option(whmc.OPT_HOP_CHUNK, 3)
     ctx.set_option(whmc.OPT_HOP_SCHEDULE, 1)
+    ctx.set_option(whmc.OPT_HOP_WG_PER_CU, 2)
     x, st = ctx.cg_solve(pack_half(ctx, b), [kappa], whmc.cg_params(tol=1e-13, check_every=4))
     assert st[0]["converged"] and rel_err(unpack_half(ctx, x), ref) < 1e-11
     x, st = ctx.cg_solve(pack_half(ctx, b), [kappa], whmc.cg_params(tol=1e-10, prec=whmc.F16, links=whmc.L12,
@@ -69,6 +77,11 @@ def test_schedule_autotuner_and_limits():
     sched, chunk, us = ctx.autotune_hop()
     assert sched in (0, 1) and 1 <= chunk <= 8 and us > 0
     assert ctx.get_option(whmc.OPT_HOP_SCHEDULE) == sched
+    assert ctx.get_option(whmc.OPT_HOP_WG_PER_CU) in (0, 2)
+    for bad in (1, 9, -1):
+        with pytest.raises(whmc.WhmcError) as e:
+            ctx.set_option(whmc.OPT_HOP_WG_PER_CU, bad)
+        assert e.value.status == 1
     # lattices without the slab schedule: L_t not divisible by 8, or slices not whole blocks
     for bad_dims in [(6, 8, 16, 16), (8, 4, 4, 4)]:
         c2 = make_ctx(bad_dims, synth.haar_links(bad_dims, 9121))

@@ -76,9 +76,13 @@ def test_streamed_cg_fp64_and_mixed():
         assert rel_err(unpack_half(ctx, x), ref) < 1e-8
 
 
-@pytest.mark.parametrize("prec,links,lanes", [(whmc.F64, whmc.L18, 2), (whmc.F64, whmc.L12, 4),
-                                              (whmc.F32, whmc.L12, 2), (whmc.F16, whmc.L12, 1)])
-def test_streamed_masked_multi_rhs_cg(prec, links, lanes):
+# multi-RHS kernels stream their links only where a launch reads each link once: one rhs group
+# (lanes x rhs per thread = 4) or group-major order; block-major order with several groups keeps
+# them cached whatever the threshold
+@pytest.mark.parametrize("prec,links,lanes,order", [(whmc.F64, whmc.L18, 2, 0), (whmc.F64, whmc.L18, 2, 1),
+                                                    (whmc.F64, whmc.L12, 4, 0), (whmc.F32, whmc.L12, 2, 1),
+                                                    (whmc.F16, whmc.L12, 1, 1)])
+def test_streamed_masked_multi_rhs_cg(prec, links, lanes, order):
     lat = Lattice(DIMS)
     U = synth.smooth_links(DIMS, 7020)
     kappas = [0.150, 0.153, 0.156, 0.1575]
@@ -86,7 +90,7 @@ def test_streamed_masked_multi_rhs_cg(prec, links, lanes):
     ctx = _ctx(U)
     nb = 2 if prec == whmc.F16 else 1
     prm = whmc.cg_params(tol=1e-12 if prec == whmc.F64 else 1e-10, prec=prec, links=links, delta=0.1, rhs_block=nb,
-                         rhs_lanes=lanes)
+                         rhs_lanes=lanes, rhs_order=order)
     x, st = ctx.cg_solve(pack_half(ctx, bs), kappas, prm)
     got = unpack_half(ctx, x, 4)
     for r, k in enumerate(kappas):
