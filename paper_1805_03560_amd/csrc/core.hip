@@ -853,9 +853,9 @@ whmc_status whmc_autotune_hop(whmc_ctx* c, int* schedule, int* chunk, double* us
   for (const auto& cd : cand) {
     c->set_schedule(cd.sched, cd.chunk);
     c->set_wg_cap(cd.cap);
-    auto pair = [&]() -> whmc_status {
-      WHMC_TRY(hop(c, WHMC_F64, WHMC_L18, 0, 0, t, x, nullptr, 0.0, 1.0, nullptr));
-      return hop(c, WHMC_F64, WHMC_L18, 1, 0, x, t, nullptr, 0.0, 1.0, nullptr);
+    auto pair = [&]() -> whmc_status {   // the hops of whmc_apply_H (non-temporal stores on large lattices)
+      WHMC_TRY(hop(c, WHMC_F64, WHMC_L18, 0, 0, t, x, nullptr, 0.0, 1.0, nullptr, true));
+      return hop(c, WHMC_F64, WHMC_L18, 1, 0, x, t, nullptr, 0.0, 1.0, nullptr, true);
     };
     float ms = 0.f;
     rc = pair();

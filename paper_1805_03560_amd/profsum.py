@@ -3,10 +3,11 @@
     python -m paper_1805_03560_amd.profsum trace DB [--top N] [--match TEXT]
         markdown table of the kernels of a `--kernel-trace` run: calls, average / min / max launch
         duration, total time, share, registers.
-    python -m paper_1805_03560_amd.profsum counters DB [--match TEXT]
+    python -m paper_1805_03560_amd.profsum counters DB [--match TEXT] [--lds BYTES]
         per-dispatch values of every counter of a `--pmc` run (summed over the counter's instances).
     python -m paper_1805_03560_amd.profsum traffic --kernel TEXT --fetch DB --write DB --copy-fetch DB \\
-            --copy-write DB --copy-bytes N [--trace DB] [--algorithmic BYTES] [--workload TEXT] [--json OUT]
+            --copy-write DB --copy-bytes N [--trace DB] [--algorithmic BYTES] [--workload TEXT] [--json OUT] \\
+            [--lds BYTES] [--last N] [--trace-last N]
         HBM bytes per launch of one kernel from a FETCH_SIZE and a WRITE_SIZE pass, each scaled by what
         the same counter reads for a device copy of N bytes (FETCH_SIZE counts the 128-byte read requests
         of gfx950 as 64 bytes, so its scale is 2).  --json writes the record bench.py reports as
@@ -42,17 +43,25 @@ def _rows(db, table):
         con.close()
 
 
-def kernels(db):
-    """[(name, duration_us, vgpr, agpr)] of every dispatch in a kernel-trace database"""
-    return [(d["name"], (d["end"] - d["start"]) / 1e3, d["vgpr_count"], d["accum_vgpr_count"])
-            for d in _rows(db, "kernels")]
+def kernels(db, lds=None):
+    """[(name, duration_us, vgpr, agpr, lds bytes)] of every dispatch in a kernel-trace database (only
+    those with that LDS allocation if lds is given)"""
+    out = []
+    for d in _rows(db, "kernels"):
+        sz = d.get("lds_size", 0) or 0
+        if lds is None or sz == lds:
+            out.append((d["name"], (d["end"] - d["start"]) / 1e3, d["vgpr_count"], d["accum_vgpr_count"], sz))
+    return out
 
 
-def counters(db):
-    """{kernel name: [{counter: value} per dispatch]} of a --pmc database, instances summed"""
+def counters(db, lds=None):
+    """{kernel name: [{counter: value} per dispatch]} of a --pmc database, instances summed (only the
+    dispatches with that LDS allocation if lds is given)"""
     per = collections.defaultdict(lambda: collections.defaultdict(float))
     names = {}
     for d in _rows(db, "counters_collection"):
+        if lds is not None and (d.get("lds_block_size", 0) or 0) != lds:
+            continue
         per[d["dispatch_id"]][d["counter_name"]] += d["value"]
         names[d["dispatch_id"]] = d["kernel_name"]
     out = collections.defaultdict(list)
@@ -66,24 +75,36 @@ def _short(name, width=110):
 
 
 def trace_table(db, top=25, match=None):
+    """kernels grouped by name and LDS allocation (a launch-time LDS reservation caps occupancy)"""
     agg = collections.defaultdict(list)
     regs = {}
-    for name, us, v, a in kernels(db):
+    for name, us, v, a, sz in kernels(db):
         if match and match not in name:
             continue
-        agg[name].append(us)
-        regs[name] = (v, a)
+        agg[(name, sz)].append(us)
+        regs[(name, sz)] = (v, a)
     total = sum(sum(v) for v in agg.values()) or 1.0
-    lines = ["| kernel | calls | avg us | min us | max us | total ms | share | VGPR / AGPR |",
-             "|---|---|---|---|---|---|---|---|"]
-    for name, v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:top]:
-        lines.append(f"| `{_short(name)}` | {len(v)} | {sum(v) / len(v):.1f} | {min(v):.1f} | {max(v):.1f} | "
-                     f"{sum(v) / 1e3:.2f} | {100 * sum(v) / total:.1f}% | {regs[name][0]} / {regs[name][1]} |")
+    lines = ["| kernel | LDS B | calls | avg us | min us | max us | total ms | share | VGPR / AGPR |",
+             "|---|---|---|---|---|---|---|---|---|"]
+    for key, v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        lines.append(f"| `{_short(key[0])}` | {key[1]} | {len(v)} | {sum(v) / len(v):.1f} | {min(v):.1f} | "
+                     f"{max(v):.1f} | {sum(v) / 1e3:.2f} | {100 * sum(v) / total:.1f}% | {regs[key][0]} / {regs[key][1]} |")
     return "\n".join(lines)
 
 
-def _one(db, counter, match):
-    vals = [c[counter] for name, lst in counters(db).items() if match in name for c in lst if counter in c]
+def _one(db, counter, match, lds=None, last=None):
+    """average of a counter over the dispatches of the kernels matching `match` (the last `last` of
+    them in dispatch order if given: a benchmark's timed launches follow its tuning launches)"""
+    per = collections.defaultdict(float)
+    for d in _rows(db, "counters_collection"):
+        if d["counter_name"] != counter or match not in d["kernel_name"]:
+            continue
+        if lds is not None and (d.get("lds_block_size", 0) or 0) != lds:
+            continue
+        per[d["dispatch_id"]] += d["value"]
+    vals = [per[k] for k in sorted(per)]
+    if last:
+        vals = vals[-last:]
     if not vals:
         raise SystemExit(f"{db}: no {counter} values for a kernel matching {match!r}")
     return sum(vals) / len(vals), len(vals)
@@ -102,8 +123,10 @@ def traffic(a):
     copy_w = max(c["WRITE_SIZE"] for c in counters(a.copy_write)[ck_w])
     fs = a.copy_bytes / (copy_f * 1024.0)
     ws = a.copy_bytes / (copy_w * 1024.0)
-    f_kib, nf = _one(a.fetch, "FETCH_SIZE", a.kernel)
-    w_kib, nw = _one(a.write, "WRITE_SIZE", a.kernel)
+    lds = getattr(a, "lds", None)
+    last = getattr(a, "last", None)
+    f_kib, nf = _one(a.fetch, "FETCH_SIZE", a.kernel, lds, last)
+    w_kib, nw = _one(a.write, "WRITE_SIZE", a.kernel, lds, last)
     rd, wr = f_kib * 1024.0 * fs, w_kib * 1024.0 * ws
     rec = {"kernel": next(n for n in counters(a.fetch) if a.kernel in n), "workload": a.workload,
            "fetch_kib": round(f_kib, 2), "write_kib": round(w_kib, 2), "dispatches": [nf, nw],
@@ -116,8 +139,12 @@ def traffic(a):
         lines.append(f"- algorithmic bytes per launch {a.algorithmic / 1e9:.3f} GB; measured / algorithmic = "
                      f"{(rd + wr) / a.algorithmic:.3f}")
         rec["algorithmic_bytes"] = int(a.algorithmic)
+    if lds is not None:
+        rec["lds_bytes"] = lds
     if a.trace:
-        durs = [us for name, us, _, _ in kernels(a.trace) if a.kernel in name]
+        durs = [us for name, us, _, _, _ in kernels(a.trace, lds) if a.kernel in name]
+        if durs and getattr(a, "trace_last", None):
+            durs = durs[-a.trace_last:]
         if durs:
             avg = sum(durs) / len(durs)
             rec["avg_launch_us"] = round(avg, 3)
@@ -142,6 +169,7 @@ def main(argv=None):
     c = sub.add_parser("counters")
     c.add_argument("db")
     c.add_argument("--match")
+    c.add_argument("--lds", type=int)
     f = sub.add_parser("traffic")
     for k in ("kernel", "fetch", "write", "copy_fetch", "copy_write"):
         f.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
@@ -150,11 +178,14 @@ def main(argv=None):
     f.add_argument("--algorithmic", type=float)
     f.add_argument("--workload", default="")
     f.add_argument("--json")
+    f.add_argument("--lds", type=int, help="only dispatches with this LDS allocation (bytes)")
+    f.add_argument("--last", type=int, help="only the last N matching dispatches of each counter pass")
+    f.add_argument("--trace-last", type=int, help="only the last N matching launches of the trace")
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         print(trace_table(a.db, a.top, a.match))
     elif a.cmd == "counters":
-        for name, lst in counters(a.db).items():
+        for name, lst in counters(a.db, a.lds).items():
             if a.match and a.match not in name:
                 continue
             print(f"{_short(name)}: {len(lst)} dispatches")
