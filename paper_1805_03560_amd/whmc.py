@@ -428,7 +428,8 @@ class Context:
         return out
 
     def autotune_hop(self):
-        """-> (schedule, chunk, microseconds per hop) of the fastest single-RHS stencil schedule"""
+        """-> (schedule, chunk, microseconds per hop) of the fastest single-RHS stencil schedule; the
+        occupancy cap it chose is get_option(OPT_HOP_WG_PER_CU)"""
         sc, ch, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         _check(lib().whmc_autotune_hop(self._h, ctypes.byref(sc), ctypes.byref(ch), ctypes.byref(us)))
         return sc.value, ch.value, us.value
