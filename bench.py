@@ -55,7 +55,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="only the timed apply_H region")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a device copy of 2 GiB (counter calibration for rocprofv3 --pmc)")
-    ap.add_argument("--profile-kernel", choices=["hop_f16_l12", "mhop_f64_12rhs", "mhop_f16_12rhs", "pf_force_24"],
+    ap.add_argument("--profile-kernel", choices=["hop_f16_l12", "hop_formats", "mhop_f64_12rhs", "mhop_f16_12rhs",
+                                                 "pf_force_24"],
                     help="only run a short workload of one kernel (for rocprofv3 counter passes) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -151,6 +152,7 @@ def main():
 def profile_kernel(name, whmc, torch, np):
     """a few launches of one kernel on its benchmark workload, for counter passes:
     hop_f16_l12: the chained FP16 even/odd pair (12-real links) on 32^3 x 64;
+    hop_formats: the chained pair in every storage format on 32^3 x 64 (3 timed steps each);
     mhop_f64_12rhs / mhop_f16_12rhs: the multi-RHS hop for 12 right-hand sides on 24^3 x 48 with the
     autotuned blocking; pf_force_24: the pair force of 24 (X, Y) pairs (kappa^4 filter, n_t = 23)
     on 32^3 x 64."""
@@ -172,6 +174,15 @@ def profile_kernel(name, whmc, torch, np):
                                whmc.F64, whmc.F16)
         us = chained_pair_us(ctx, torch, ctx.stream, whmc.F16, whmc.L12, x, steps=5, warmup=2)
         info = {"us_per_hop": us}
+    elif name == "hop_formats":
+        x64 = ctx.pack_spinor(torch.from_numpy(synth.gaussian_spinor(Vh, 3002)).to(dev), 1)
+        info = {}
+        for (p, pn), links in [((whmc.F64, "f64"), 18), ((whmc.F64, "f64"), 12), ((whmc.F64, "f64"), 8),
+                               ((whmc.F32, "f32"), 12), ((whmc.F32, "f32"), 8), ((whmc.F16, "f16"), 12),
+                               ((whmc.F16, "f16"), 8)]:
+            xin = x64.clone() if p == whmc.F64 else ctx.convert_spinor(x64, whmc.F64, p)
+            info[f"{pn}-{links}_us_per_hop"] = round(chained_pair_us(ctx, torch, ctx.stream, p, links, xin, steps=3,
+                                                                     warmup=1), 1)
     elif name.startswith("mhop"):
         n = 12
         prec, links = (whmc.F64, whmc.L18) if "f64" in name else (whmc.F16, whmc.L12)
