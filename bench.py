@@ -267,18 +267,22 @@ def extras(ctx, whmc, torch, np, stream, Vh):
                       ("mixed_f16_l12", MIXED_F16(whmc)),
                       ("mixed_f16_l8", MIXED_F16(whmc, whmc.L8))]:
         ctx.cg_solve(b, [KAPPA], prm)      # warm-up of this path
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        x, st = ctx.cg_solve(b, [KAPPA], prm)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
+        times = []
+        for _ in range(3):                  # best of three solves (each one's host checks add jitter)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            x, st = ctx.cg_solve(b, [KAPPA], prm)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = min(times)
         err = float(torch.linalg.vector_norm(x - ref) / torch.linalg.vector_norm(ref))
         s = st[0]
         t[name] = ms
-        cgr[name] = {"ms": round(ms, 2), "iters": s["iters"], "reliable_updates": s["reliable_updates"],
-                     "true_residual": s["true_residual"], "rel_err_vs_fp64_solution": err}
+        cgr[name] = {"ms": round(ms, 2), "ms_of_3_solves": [round(v, 2) for v in times], "iters": s["iters"],
+                     "reliable_updates": s["reliable_updates"], "true_residual": s["true_residual"],
+                     "rel_err_vs_fp64_solution": err}
         if golden is not None:
             cgr[name]["rel_err_vs_oracle"] = err_vs_golden(ctx, x, golden, np)["rel_err_sampled"]
         log(f"[bench] CG {name}: {ms:.1f} ms, {s['iters']} iters, res {s['true_residual']:.2e}, err {err:.2e}, "

@@ -104,12 +104,13 @@ whmc_status whmc_set_stream(whmc_ctx* ctx, void* stream);
  *                              1 = one thread per site and its four links.
  *   WHMC_OPT_FORCE_CHUNK       (X, Y) pairs summed per launch of that contraction, 1 .. 24 (default
  *                              24); later launches accumulate.  Results agree to rounding.
- *   WHMC_OPT_HOP_WG_PER_CU     occupancy cap of those kernels that work on FP64 spinors: 0 = none
- *                              (default), 2 .. 8 = at most that many 128-thread workgroups per
- *                              compute unit (each reserves LDS it does not use).  Fewer sites in
- *                              flight keep their neighbour spinors in the L2 of their XCD.  The
- *                              FP32 / FP16 kernels are never capped.  EARG if the device's LDS
- *                              limits do not allow the value.  Results do not depend on it. */
+ *   WHMC_OPT_HOP_WG_PER_CU     occupancy cap of those kernels that work on FP64 spinors with 18- or
+ *                              12-real links: 0 = none (default), 2 .. 8 = at most that many
+ *                              128-thread workgroups per compute unit (each reserves LDS it does not
+ *                              use).  Fewer sites in flight keep their neighbour spinors in the L2
+ *                              of their XCD.  FP32 / FP16 kernels and 8-real links are never capped.
+ *                              EARG if the device's LDS limits do not allow the value.  Results do
+ *                              not depend on it. */
 #define WHMC_OPT_HOP_SCHEDULE 2
 #define WHMC_OPT_HOP_CHUNK 3
 #define WHMC_OPT_FORCE_KERNEL 4

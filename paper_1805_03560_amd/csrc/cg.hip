@@ -276,8 +276,9 @@ static SpinorF16 s16(void* p, int Vh) { return SpinorF16{(uint4*)p, (float*)((ui
 template <class Lnk, class S, class SR, bool MIXED>
 static whmc_status enqueue_iters(whmc_ctx* c, const Lnk& L, S p, S t, S u, S v, SR r, SR x, double kappa, int n) {
   const dim3 grid(c->site_blocks()), block(kBlock);
-  // occupancy cap of the FP64 stencil kernels (the low-precision ones need every wave)
-  const unsigned lds = std::is_same<S, SpinorF64>::value ? c->stencil_lds : 0u;
+  // occupancy cap of the FP64 stencil kernels with 18- or 12-real links (the low-precision and 8-real
+  // ones need every wave)
+  const unsigned lds = std::is_same<S, SpinorF64>::value && !is_8real<Lnk>::value ? c->stencil_lds : 0u;
   const double k2 = kappa * kappa;
   for (int it = 0; it < n; ++it) {
     TraceRange tr(MIXED ? "whmc cg iteration (mixed)" : "whmc cg iteration");

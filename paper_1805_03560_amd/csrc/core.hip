@@ -86,8 +86,9 @@ template <class Lnk, class S>
 static whmc_status launch_hop(whmc_ctx* c, const Lnk& L, int par, int dag, S in, S x, S out, bool xpay, double a,
                               double b, double* norm_out, bool nts) {
   dim3 grid(c->site_blocks()), block(kBlock);
-  // the occupancy cap applies to FP64 spinors only (the low-precision kernels need every wave)
-  const unsigned lds = std::is_same<S, SpinorF64>::value ? c->stencil_lds : 0u;
+  // the occupancy cap applies to FP64 spinors with 18- or 12-real links only (the low-precision and
+  // 8-real kernels carry more arithmetic per byte and need every wave)
+  const unsigned lds = std::is_same<S, SpinorF64>::value && !is_8real<Lnk>::value ? c->stencil_lds : 0u;
 #define WHMC_L(D, XP, N, NS) hipLaunchKernelGGL((k_hop<D, XP, N, NS, Lnk, S, S, S>), grid, block, lds, \
                                                 c->stream, c->g, \
                                                 par, L, in, x, out, a, b, c->red, norm_out)
@@ -160,12 +161,13 @@ __global__ __launch_bounds__(kBlock) void k_hop_full(Geom g, Lnk L, S in_e, S in
 template <class Lnk, class S>
 static whmc_status launch_full(whmc_ctx* c, const Lnk& L, int dag, S ie, S io, S oe, S oo, bool nts) {
   dim3 grid(2 * c->stencil_blocks()), block(kBlock);
+  const unsigned lds = std::is_same<S, SpinorF64>::value && !is_8real<Lnk>::value ? c->stencil_lds : 0u;
   if (dag) {
-    if (nts) hipLaunchKernelGGL((k_hop_full<1, true, Lnk, S>), grid, block, 0, c->stream, c->g, L, ie, io, oe, oo);
-    else hipLaunchKernelGGL((k_hop_full<1, false, Lnk, S>), grid, block, 0, c->stream, c->g, L, ie, io, oe, oo);
+    if (nts) hipLaunchKernelGGL((k_hop_full<1, true, Lnk, S>), grid, block, lds, c->stream, c->g, L, ie, io, oe, oo);
+    else hipLaunchKernelGGL((k_hop_full<1, false, Lnk, S>), grid, block, lds, c->stream, c->g, L, ie, io, oe, oo);
   } else {
-    if (nts) hipLaunchKernelGGL((k_hop_full<0, true, Lnk, S>), grid, block, 0, c->stream, c->g, L, ie, io, oe, oo);
-    else hipLaunchKernelGGL((k_hop_full<0, false, Lnk, S>), grid, block, 0, c->stream, c->g, L, ie, io, oe, oo);
+    if (nts) hipLaunchKernelGGL((k_hop_full<0, true, Lnk, S>), grid, block, lds, c->stream, c->g, L, ie, io, oe, oo);
+    else hipLaunchKernelGGL((k_hop_full<0, false, Lnk, S>), grid, block, lds, c->stream, c->g, L, ie, io, oe, oo);
   }
   WHMC_HIP(hipGetLastError());
   return WHMC_OK;

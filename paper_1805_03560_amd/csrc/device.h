@@ -21,6 +21,8 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #define WHMC_DEV __device__ __forceinline__
 
 namespace whmc {
@@ -105,7 +107,45 @@ template <typename R> WHMC_DEV void reconstruct_row2(SU3<R>& U) {
 // sqrt(n - |stored|^2) >= sqrt(n / 2), then suffers no cancellation.  The choice is flagged by
 // storing the phase plus 8 (phases lie in [-pi, pi]).  A link with n = 0 (U00 of modulus 1) has no
 // such form; the derivation of the format rejects fields with such links.
-WHMC_DEV void phase(double t, cplx<double>& e) { sincos(t, &e.im, &e.re); }
+// Double precision: e^{it} for |t| <= pi + 1e-6 (the stored phases), without the general library
+// routine, whose reduction of arbitrary arguments needs many registers.  Cody-Waite reduction
+// (W. J. Cody and W. Waite, Software Manual for the Elementary Functions, 1980): t = k pi/2 + r with
+// k = rint(2t / pi) in {-2, ..., 2} and pi/2 split into a head (the double nearest to pi/2) and a
+// tail, so that t - k * head is exact (Sterbenz) and |r| <= pi/4 (1 + 1e-16).  Then the Taylor series
+// of sin r and cos r up to r^17 / 17! and r^18 / 18!, whose first omitted terms are below 2e-19 on
+// that range, summed by Horner's rule in r^2; the quadrant k mod 4 permutes and signs the results.
+WHMC_DEV void phase(double t, cplx<double>& e) {
+  constexpr double two_over_pi = 0.63661977236758134308;
+  constexpr double pio2_hi = 1.5707963267948966192;     // the double nearest to pi / 2
+  constexpr double pio2_lo = 6.1232339957367658e-17;    // pi / 2 - pio2_hi
+  const double k = rint(t * two_over_pi);
+  const double r = (t - k * pio2_hi) - k * pio2_lo;
+  const double r2 = r * r;
+  // sin r = r (1 - r^2/3! + r^4/5! - ... + r^16/17!), cos r = 1 - r^2/2! + ... + r^18/18!
+  double sp = 1.0 / 355687428096000.0;                  // 1 / 17!
+  sp = fma(sp, r2, -1.0 / 1307674368000.0);             // 1 / 15!
+  sp = fma(sp, r2, 1.0 / 6227020800.0);                 // 1 / 13!
+  sp = fma(sp, r2, -1.0 / 39916800.0);                  // 1 / 11!
+  sp = fma(sp, r2, 1.0 / 362880.0);                     // 1 / 9!
+  sp = fma(sp, r2, -1.0 / 5040.0);                      // 1 / 7!
+  sp = fma(sp, r2, 1.0 / 120.0);                        // 1 / 5!
+  sp = fma(sp, r2, -1.0 / 6.0);                         // 1 / 3!
+  const double sn = fma(r * r2, sp, r);
+  double cp = 1.0 / 6402373705728000.0;                 // 1 / 18!
+  cp = fma(cp, r2, -1.0 / 20922789888000.0);            // 1 / 16!
+  cp = fma(cp, r2, 1.0 / 87178291200.0);                // 1 / 14!
+  cp = fma(cp, r2, -1.0 / 479001600.0);                 // 1 / 12!
+  cp = fma(cp, r2, 1.0 / 3628800.0);                    // 1 / 10!
+  cp = fma(cp, r2, -1.0 / 40320.0);                     // 1 / 8!
+  cp = fma(cp, r2, 1.0 / 720.0);                        // 1 / 6!
+  cp = fma(cp, r2, -1.0 / 24.0);                        // 1 / 4!
+  cp = fma(cp, r2, 0.5);                                // 1 / 2!
+  const double cs = fma(-r2, cp, 1.0);
+  const int q = (int)k & 3;   // two's complement: -1 -> 3, -2 -> 2
+  const double s_ = (q & 1) ? cs : sn, c_ = (q & 1) ? sn : cs;
+  e.im = (q & 2) ? -s_ : s_;
+  e.re = ((q + 1) & 2) ? -c_ : c_;
+}
 // single precision: the hardware sine / cosine (absolute error about 5e-7 on [-pi, pi], the range
 // the stored phases lie in), below the rounding of the FP32 / FP16 formats themselves
 WHMC_DEV void phase(float t, cplx<float>& e) { __sincosf(t, &e.im, &e.re); }
@@ -541,6 +581,12 @@ struct LinkF16_8T {
     reconstruct8(U, b1, pi * h2f((unsigned short)(w.w & 0xffffu)), pi * h2f((unsigned short)(w.w >> 16)));
   }
 };
+
+// 8-real accessors (their reconstruction makes the hop arithmetic-heavy: not occupancy-capped)
+template <class L> struct is_8real : std::false_type {};
+template <bool NT> struct is_8real<LinkF64_8T<NT>> : std::true_type {};
+template <bool NT> struct is_8real<LinkF32_8T<NT>> : std::true_type {};
+template <bool NT> struct is_8real<LinkF16_8T<NT>> : std::true_type {};
 
 using LinkF64_18 = LinkF64_18T<false>;
 using LinkF64_12 = LinkF64_12T<false>;

@@ -89,6 +89,10 @@ def trace_table(db, top=25, match=None):
     for key, v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:top]:
         lines.append(f"| `{_short(key[0])}` | {key[1]} | {len(v)} | {sum(v) / len(v):.1f} | {min(v):.1f} | "
                      f"{max(v):.1f} | {sum(v) / 1e3:.2f} | {100 * sum(v) / total:.1f}% | {regs[key][0]} / {regs[key][1]} |")
+    lines.append("")
+    lines.append("(VGPR / AGPR: rocprofv3's vgpr_count / accum_vgpr_count; on gfx950 vgpr_count is half the registers "
+                 "allocated per lane, architectural and accumulation together, so the compiler's resource report "
+                 "gives about twice it.)")
     return "\n".join(lines)
 
 

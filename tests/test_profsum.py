@@ -32,7 +32,9 @@ def _pmc_db(path, rows):
 def test_trace_table_statistics(tmp_path):
     db = str(tmp_path / "t.db")
     _trace_db(db, [("k_hop<0>", 280.0), ("k_hop<0>", 290.0), ("k_fill", 2.0)])
-    rows = [r for r in profsum.trace_table(db).splitlines() if r.startswith("| `")]
+    text = profsum.trace_table(db)
+    assert "vgpr_count" in text.splitlines()[-1]
+    rows = [r for r in text.splitlines() if r.startswith("| `")]
     assert rows[0].startswith("| `k_hop<0>` | 0 | 2 | 285.0 | 280.0 | 290.0 | 0.57 |")
     assert "| `k_fill` | 0 | 1 | 2.0 |" in rows[1]
 
