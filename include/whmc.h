@@ -121,7 +121,8 @@ whmc_status whmc_get_option(const whmc_ctx* ctx, int option, long long* value);
 
 /* Autotuner of the single-RHS stencil schedule: times the FP64 even/odd hop pair (H_eo then H_oe,
  * 18-real links) for schedule 0 and for schedule 1 with chunks of 1/16 .. 1/2 of a time slice, each
- * without and with a cap of 2 workgroups per compute unit, and keeps the fastest in the context
+ * without and with a cap of 2 workgroups per compute unit (each candidate's best of four interleaved
+ * rounds of eight pairs), and keeps the fastest in the context
  * (WHMC_OPT_HOP_SCHEDULE / WHMC_OPT_HOP_CHUNK / WHMC_OPT_HOP_WG_PER_CU, read back with
  * whmc_get_option).  Outputs may be NULL; us receives the time per hop in microseconds.  Uses context
  * scratch of two half fields.  On an error the schedule and cap are left as they were. */

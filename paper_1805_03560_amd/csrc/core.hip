@@ -1,4 +1,5 @@
 // Context, gauge storage, layout conversion, the hopping-matrix launchers and FP64 BLAS.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -849,32 +850,34 @@ whmc_status whmc_autotune_hop(whmc_ctx* c, int* schedule, int* chunk, double* us
   WHMC_HIP(hipEventCreate(&e0));
   WHMC_HIP(hipEventCreate(&e1));
   const Geom saved = c->g;
-  double best = 1e30;
-  Cand pick = cand[0];
+  // every candidate is timed in each of kRounds rounds (rounds interleave the candidates, so clock
+  // and temperature drifts hit all of them alike) and keeps its best round: the differences between
+  // candidates (a few per cent) are below the spread of a single short timing
+  constexpr int kRounds = 4, kPairs = 8;
+  std::vector<double> best_us(cand.size(), 1e30);
   whmc_status rc = WHMC_OK;
-  for (const auto& cd : cand) {
-    c->set_schedule(cd.sched, cd.chunk);
-    c->set_wg_cap(cd.cap);
-    auto pair = [&]() -> whmc_status {   // the hops of whmc_apply_H (non-temporal stores on large lattices)
-      WHMC_TRY(hop(c, WHMC_F64, WHMC_L18, 0, 0, t, x, nullptr, 0.0, 1.0, nullptr, true));
-      return hop(c, WHMC_F64, WHMC_L18, 1, 0, x, t, nullptr, 0.0, 1.0, nullptr, true);
-    };
-    float ms = 0.f;
-    rc = pair();
-    for (int rep = 0; rep < 5 && rc == WHMC_OK; ++rep) {
-      if (rep == 0 && hipEventRecord(e0, c->stream) != hipSuccess) rc = WHMC_EHIP;
-      if (rc == WHMC_OK) rc = pair();
+  auto pair = [&]() -> whmc_status {   // the hops of whmc_apply_H (non-temporal stores on large lattices)
+    WHMC_TRY(hop(c, WHMC_F64, WHMC_L18, 0, 0, t, x, nullptr, 0.0, 1.0, nullptr, true));
+    return hop(c, WHMC_F64, WHMC_L18, 1, 0, x, t, nullptr, 0.0, 1.0, nullptr, true);
+  };
+  for (int round = 0; round < kRounds && rc == WHMC_OK; ++round)
+    for (size_t q = 0; q < cand.size() && rc == WHMC_OK; ++q) {
+      c->set_schedule(cand[q].sched, cand[q].chunk);
+      c->set_wg_cap(cand[q].cap);
+      float ms = 0.f;
+      rc = pair();   // warm-up of this candidate
+      if (rc == WHMC_OK && hipEventRecord(e0, c->stream) != hipSuccess) rc = WHMC_EHIP;
+      for (int rep = 0; rep < kPairs && rc == WHMC_OK; ++rep) rc = pair();
+      if (rc == WHMC_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = WHMC_EHIP;
+      if (rc == WHMC_OK) best_us[q] = std::min(best_us[q], ms * 1e3 / (2.0 * kPairs));
     }
-    if (rc == WHMC_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-      rc = WHMC_EHIP;
-    if (rc != WHMC_OK) break;
-    const double per_hop = ms * 1e3 / 10.0;
-    if (per_hop < best) {
-      best = per_hop;
-      pick = cd;
-    }
-  }
+  size_t qbest = 0;
+  for (size_t q = 1; q < cand.size(); ++q)
+    if (best_us[q] < best_us[qbest]) qbest = q;
+  const Cand pick = cand[qbest];
+  const double best = best_us[qbest];
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->g = saved;
