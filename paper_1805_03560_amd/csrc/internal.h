@@ -12,6 +12,7 @@
 
 #include "../../include/whmc.h"
 #include "device.h"
+#include "occupancy.h"
 
 namespace whmc {
 
@@ -125,19 +126,17 @@ struct whmc_ctx {
   // grid of the single-RHS stencil kernels (site_block), for the schedule in g.sched
   int site_blocks() const { return g.sched == 1 ? 8 * g.tx * g.nch * g.tq : stencil_blocks(); }
   // at most k workgroups per compute unit for the single-RHS stencil kernels (k = 0: no cap; else
-  // 2 <= k <= 8): reserve the smallest multiple of 2 KiB above lds_per_cu / (k + 1) bytes, so that
-  // k workgroups fit and k + 1 do not (false, unchanged, if the device cannot do it)
+  // 2 <= k <= 8, reserving whmc::lds_reservation bytes; false, unchanged, if the device cannot do it)
   bool set_wg_cap(int k) {
     if (k == 0) {
       hop_wg_per_cu = 0;
       stencil_lds = 0;
       return true;
     }
-    if (k < 2 || k > 8 || lds_per_cu <= 0) return false;
-    const long long b = ((long long)lds_per_cu / (k + 1) + 1 + 2047) / 2048 * 2048;
-    if (b * k > lds_per_cu || b * (k + 1) <= lds_per_cu || b > lds_per_wg) return false;
+    const unsigned b = whmc::lds_reservation(lds_per_cu, lds_per_wg, k);
+    if (b == 0) return false;
     hop_wg_per_cu = k;
-    stencil_lds = (unsigned)b;
+    stencil_lds = b;
     return true;
   }
   // time-slab schedule with chunks of tq blocks, if the lattice allows it (else false, unchanged)

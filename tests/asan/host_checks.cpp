@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "whmc.h"
+#include "../../paper_1805_03560_amd/csrc/occupancy.h"
 
 static int g_checks = 0;
 
@@ -189,12 +190,35 @@ static void create_arguments() {
   EXPECT(whmc_abi_version() == WHMC_ABI_VERSION);
 }
 
+// the LDS reservation of the occupancy cap: k workgroups fit, k + 1 do not, for every k and any
+// plausible LDS size; impossible requests give 0
+static void lds_reservation() {
+  int possible = 0;
+  for (long long cu = 32768; cu <= 262144; cu += 1024)
+    for (int k = 2; k <= 8; ++k) {
+      const unsigned b = whmc::lds_reservation(cu, cu, k);
+      if (b == 0) continue;
+      ++possible;
+      EXPECT(b % 2048 == 0);
+      EXPECT(((long long)b + 2048) * k <= cu);   // k fit even with each allocation rounded up by 2 KiB
+      EXPECT((long long)b * (k + 1) > cu);       // k + 1 never fit
+    }
+  EXPECT(possible > 1000);
+  for (int k : {2, 3, 4, 5, 6, 8}) EXPECT(whmc::lds_reservation(163840, 163840, k) > 0);   // gfx950: 160 KiB per CU
+  EXPECT(whmc::lds_reservation(163840, 65536, 2) == 55296);
+  EXPECT(whmc::lds_reservation(163840, 65536, 1) == 0);
+  EXPECT(whmc::lds_reservation(163840, 65536, 9) == 0);
+  EXPECT(whmc::lds_reservation(0, 65536, 2) == 0);
+  EXPECT(whmc::lds_reservation(163840, 16384, 2) == 0);   // more than one workgroup may allocate
+}
+
 int main() {
   filter_coefficients();
   rooted_coefficients();
   masspre_coefficients();
   null_context();
   create_arguments();
+  lds_reservation();
   std::printf("host checks passed: %d\n", g_checks);
   return 0;
 }
