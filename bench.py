@@ -461,7 +461,9 @@ def multi_rhs(whmc, torch, stream):
         ref, _ = ctx.cg_solve(b, kappas, whmc.cg_params(tol=1e-12))
         ref = ref.clone()
         for name, prm in [("multi_fp64", whmc.cg_params(tol=1e-10)),
+                          ("multi_fp64_l8", whmc.cg_params(tol=1e-10, links=whmc.L8)),
                           ("multi_mixed_f32_l12", MIXED_F32(whmc)),
+                          ("multi_mixed_f32_l8", MIXED_F32(whmc, whmc.L8)),
                           ("multi_mixed_f16_l12", MIXED_F16(whmc))]:
             ctx.cg_solve(b, kappas, prm)
             holder = {}
@@ -481,7 +483,8 @@ def multi_rhs(whmc, torch, stream):
         log(f"[bench] multi-RHS {nrhs}: hop us/rhs f64 {row['hop_f64_us_per_rhs']} {row['hop_f64_blocking']}, f32 "
             f"{row['hop_f32_l12_us_per_rhs']} {row['hop_f32_l12_blocking']}, f16 {row['hop_f16_l12_us_per_rhs']} "
             f"{row['hop_f16_l12_blocking']}; seq {t_seq:.1f} ms, "
-            f"multi fp64 {row['multi_fp64']['ms']} ms, mixed f32 {row['multi_mixed_f32_l12']['ms']} ms, "
+            f"multi fp64 {row['multi_fp64']['ms']} ms (8-real {row['multi_fp64_l8']['ms']} ms), mixed f32 "
+            f"{row['multi_mixed_f32_l12']['ms']} ms (8-real {row['multi_mixed_f32_l8']['ms']} ms), "
             f"mixed f16 {row['multi_mixed_f16_l12']['ms']} ms")
     ctx.close()
     return res
@@ -490,7 +493,8 @@ def multi_rhs(whmc, torch, stream):
 def hmc_section(ctx, whmc, torch, stream, Vh):
     """32^3 x 64 HMC (beta = 5.6, kappa = 0.1575, kappa^4 filter with n_t = 15, n_max = 29, Omelyan
     lambda = 1/6, gauge on 4 fine steps per coarse step, tau = 1): one trajectory with mixed FP16
-    MD solves, Delta H at m = 10 and 20, reversibility, and a central finite difference of the
+    MD solves, one with the kappa^2 filter (n_t = 7, n_max = 19) and the leapfrog integrator at
+    m = 20, Delta H at m = 10 and 20, reversibility, and a central finite difference of the
     total action along a random algebra direction against the force."""
     import math
     from paper_1805_03560_amd import synth
@@ -509,6 +513,20 @@ def hmc_section(ctx, whmc, torch, stream, Vh):
                              "accepted": res["accepted"], "plaquette": res["plaquette"],
                              "cg_iters": res["cg_iters"], "n_solves": res["n_solves"]}
     log(f"[bench] HMC 32^3x64 trajectory: {out['trajectory_m10']}")
+    # the kappa^2 filter (n_t = 7, n_max = 19) with the leapfrog integrator, m = 20 coarse steps
+    ctx.load_gauge(U0, unitarity_tol=0.0)
+    p2 = whmc.hmc_params(beta=5.6, kappa=KAPPA, k=1, n_t=7, n_max=19, integrator=whmc.LEAPFROG, lam=0.0, m=20, m0=4,
+                         tau=1.0, md_solver=md_mixed, action_solver=fp64_tight)
+    t0 = time.perf_counter()
+    res = ctx.hmc_trajectory(p2, pi0, eta, 0.5)
+    out["trajectory_leapfrog_kappa2_m20"] = {
+        "seconds": round(time.perf_counter() - t0, 3), "dH": res["dH"], "accepted": res["accepted"],
+        "plaquette": res["plaquette"], "cg_iters": res["cg_iters"], "n_solves": res["n_solves"],
+        "note": "timing of one trajectory's kernels; the smooth synthetic field (plaquette 0.79) is far from the "
+                "beta = 5.6 equilibrium (about 0.57) and its gauge force is large, which the second-order leapfrog "
+                "at m = 20 integrates poorly, so |dH| is large; the paper's 12^3x24 leapfrog runs at equilibrium "
+                "are reproduced by the ensemble runs"}
+    log(f"[bench] HMC 32^3x64 leapfrog kappa^2 trajectory: {out['trajectory_leapfrog_kappa2_m20']}")
     ctx.load_gauge(U0, unitarity_tol=0.0)
     phi = ctx.heatbath_phi(eta, 2, 15, 29, KAPPA)
     dh = {}

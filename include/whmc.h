@@ -169,9 +169,9 @@ whmc_status whmc_apply_H(whmc_ctx* ctx, void* out, const void* in, int out_parit
  *     reused from its L2 (each link read from memory once per call);
  *   1 (group-major): each group sweeps the whole lattice before the next, so the neighbour
  *     spinors of the group stay in L2 (the links are read once per group).
- * Allowed: FP64 (18- or 12-real links) rhs_block = 1 with rhs_lanes = 1, 2 or 4, or rhs_block = 2 with
- * rhs_lanes = 1 or 2; FP32 / FP16
- * (12-real links) rhs_block = 1, 2 or 4 with rhs_lanes = 1 or 2.  rhs_block = rhs_lanes = 0
+ * Allowed: FP64 (18-, 12- or 8-real links) rhs_block = 1 with rhs_lanes = 1, 2 or 4, or rhs_block = 2
+ * with rhs_lanes = 1 or 2; FP32 / FP16 (12- or 8-real links) rhs_block = 1, 2 or 4 with
+ * rhs_lanes = 1 or 2; other formats WHMC_EUNSUP.  rhs_block = rhs_lanes = 0
  * takes the autotuned blocking and order (rhs_order ignored); one of them 0 reads as 1; anything
  * else is WHMC_EARG. */
 whmc_status whmc_apply_H_multi(whmc_ctx* ctx, void* out, const void* in, int out_parity, int dagger, int prec,
@@ -220,7 +220,8 @@ whmc_status whmc_apply_MdagM_noalloc(whmc_ctx* ctx, double* out, const double* i
  *     format and `links`-real links of the same precision, FP64 reliable updates recompute
  *     r = b - A x whenever the iterated residual drops below delta times its maximum since the
  *     last update; dot products accumulate in FP64.
- *   nrhs > 1: all right-hand sides advance together through the multi-RHS kernels, blocked as
+ *   nrhs > 1: all right-hand sides advance together through the multi-RHS kernels (mixed
+ *     precision with 18-real links, which they lack, solves them one after the other), blocked as
  *     in whmc_apply_H_multi (rhs_block = rhs_lanes = 0: autotuned); a converged rhs is frozen
  *     (masked) while the others continue; the FP64 true residuals of reliable updates and of
  *     the final check are computed for all right-hand sides concerned in one multi-RHS pass.

@@ -526,7 +526,19 @@ static whmc_status with_format(whmc_ctx* c, int prec, int links, bool nt, F&& f)
     if (nt) return f(LinkF16_12T<true>{c->U16_12, Vh}, h16);
     return f(LinkF16_12T<false>{c->U16_12, Vh}, h16);
   }
-  set_error("multi-RHS kernels support FP64 with 18- or 12-real links and FP32 / FP16 with 12-real links");
+  if (prec == WHMC_F64 && links == WHMC_L8) {
+    if (nt) return f(LinkF64_8T<true>{c->U8, Vh}, h64);
+    return f(LinkF64_8T<false>{c->U8, Vh}, h64);
+  }
+  if (prec == WHMC_F32 && links == WHMC_L8) {
+    if (nt) return f(LinkF32_8T<true>{c->U32_8, Vh}, h32);
+    return f(LinkF32_8T<false>{c->U32_8, Vh}, h32);
+  }
+  if (prec == WHMC_F16 && links == WHMC_L8) {
+    if (nt) return f(LinkF16_8T<true>{c->U16_8, Vh}, h16);
+    return f(LinkF16_8T<false>{c->U16_8, Vh}, h16);
+  }
+  set_error("multi-RHS kernels support FP64 with 18-, 12- or 8-real links and FP32 / FP16 with 12- or 8-real links");
   return WHMC_EUNSUP;
 }
 
@@ -764,7 +776,7 @@ whmc_status cg_solve_multi(whmc_ctx* c, double* x, const double* b, const double
   const bool mixed = prm->prec != WHMC_F64;
   const int prec = prm->prec;
   const int links = prm->links;
-  if ((mixed && links != WHMC_L12) || links == WHMC_L8) {
+  if (mixed && links == WHMC_L18) {
     // no multi-RHS kernels for this format: solve the right-hand sides one after the other
     whmc_cg_params one = *prm;
     whmc_status worst = WHMC_OK;

@@ -99,3 +99,58 @@ def test_masked_multi_rhs_cg(prec, nrhs, nb, lanes, order, dims):
         assert rel_err(got[r], ref) < 1e-8
     # lighter quarks (larger kappa) need more iterations: the rhs converged at different times
     assert len(set(iters)) > 1, iters
+
+
+# 8-real links in the multi-RHS kernels (reconstruction of the link per site, shared by the rhs of a
+# thread and by the lanes of a site).  FP16 8-real links store the phases as theta / pi in half
+# precision (|d theta| <= pi 2^-12 = 7.7e-4) and rebuild four entries from products of three stored
+# ones, so on Haar links the format itself is good to a few 1e-3 per link: against the oracle the
+# bound is 1e-2; against the single-rhs hop of the same format (same inputs, FP32 arithmetic) 1e-3
+@pytest.mark.parametrize("prec,tol", [(whmc.F64, 1e-12), (whmc.F32, 2e-6), (whmc.F16, 1e-2)])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 8), (4, 8, 16, 16)])
+def test_multi_hop_8real_links(prec, tol, dims):
+    lat = Lattice(dims)
+    U = synth.haar_links(dims, 5040)
+    nrhs = 5
+    xs = np.stack([synth.gaussian_spinor(lat.Vh, 5041 + r) for r in range(nrhs)])
+    ctx = make_ctx(dims, U)
+    xin = pack_half(ctx, xs)
+    if prec != whmc.F64:
+        xin = ctx.convert_spinor(xin, whmc.F64, prec, nrhs)
+    blockings = [(1, 1), (1, 2), (1, 4), (2, 1), (2, 2)] if prec == whmc.F64 else LOW_PREC_BLOCKINGS
+    for nb, lanes in blockings:
+        for order in (0, 1):
+            for par, dag in [(0, 0), (1, 1)]:
+                out = ctx.apply_H_multi(xin, par, nrhs, dagger=dag, prec=prec, links=whmc.L8, rhs_block=nb,
+                                        rhs_lanes=lanes, rhs_order=order)
+                if prec != whmc.F64:
+                    out = ctx.convert_spinor(out, prec, whmc.F64, nrhs)
+                got = unpack_half(ctx, out, nrhs).reshape(nrhs, lat.Vh, 4, 3)
+                for r in range(nrhs):
+                    assert rel_err(got[r], dirac.apply_Hblock(lat, U, xs[r], par, dagger=bool(dag))) < tol
+                if prec == whmc.F16:
+                    for r in range(nrhs):
+                        one = ctx.apply_H(ctx.convert_spinor(pack_half(ctx, xs[r]), whmc.F64, prec), par,
+                                          dagger=dag, prec=prec, links=whmc.L8)
+                        single = unpack_half(ctx, ctx.convert_spinor(one, prec, whmc.F64)).reshape(lat.Vh, 4, 3)
+                        assert rel_err(got[r], single) < 1e-3
+
+
+@pytest.mark.parametrize("prec,nrhs,nb,lanes,order", [(whmc.F64, 5, 1, 2, 0), (whmc.F64, 4, 0, 0, 0),
+                                                      (whmc.F32, 4, 0, 0, 0), (whmc.F16, 6, 2, 2, 1)])
+def test_masked_multi_rhs_cg_8real_links(prec, nrhs, nb, lanes, order):
+    dims = (4, 8, 16, 16)
+    lat = Lattice(dims)
+    U = synth.smooth_links(dims, 5050)
+    kappas = [KAPPAS[r % 4] for r in range(nrhs)]
+    bs = np.stack([synth.gaussian_spinor(lat.Vh, 5051 + r) for r in range(nrhs)])
+    ctx = make_ctx(dims, U)
+    tol = 1e-12 if prec == whmc.F64 else 1e-10
+    prm = whmc.cg_params(tol=tol, prec=prec, links=whmc.L8, delta=0.1, rhs_block=nb, rhs_lanes=lanes,
+                         rhs_order=order)
+    x, st = ctx.cg_solve(pack_half(ctx, bs), kappas, prm)
+    got = unpack_half(ctx, x, nrhs).reshape(nrhs, lat.Vh, 4, 3)
+    for r, k in enumerate(kappas):
+        ref, _, _ = cg(lambda v: dirac.apply_MooDagMoo(lat, U, v, k), bs[r], tol=1e-14)
+        assert st[r]["converged"] and st[r]["true_residual"] <= tol
+        assert rel_err(got[r], ref) < (1e-10 if prec == whmc.F64 else 1e-8)
