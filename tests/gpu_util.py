@@ -45,3 +45,16 @@ def rel_err(a, b):
 
 def algebra_to_numpy(ctx, buf):
     return ctx.unpack_algebra(buf).cpu().numpy()
+
+
+_ORACLE_CACHE = {}
+
+
+def oracle_cached(key, compute):
+    """compute(), an oracle reference, evaluated once per test session for a hashable key that names
+    everything it depends on (the generator, seeds and parameters the test builds its inputs from):
+    parametrizations of a test that vary only the GPU side (blocking, kernel variant, format) share
+    the reference instead of recomputing it"""
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = compute()
+    return _ORACLE_CACHE[key]

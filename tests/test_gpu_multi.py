@@ -8,7 +8,7 @@ from oracle.lattice import Lattice
 from oracle.solve import cg
 from paper_1805_03560_amd import synth, whmc
 
-from gpu_util import make_ctx, pack_half, rel_err, unpack_half
+from gpu_util import make_ctx, oracle_cached, pack_half, rel_err, unpack_half
 
 pytestmark = pytest.mark.gpu
 
@@ -94,7 +94,8 @@ def test_masked_multi_rhs_cg(prec, nrhs, nb, lanes, order, dims):
     got = unpack_half(ctx, x, nrhs).reshape(nrhs, lat.Vh, 4, 3)
     iters = [s["iters"] for s in st]
     for r, k in enumerate(kappas):
-        ref, _, _ = cg(lambda v: dirac.apply_MooDagMoo(lat, U, v, k), bs[r], tol=1e-14)
+        ref = oracle_cached(("moo_cg", dims, "smooth", 5030, 4000 + r, k),
+                            lambda: cg(lambda v: dirac.apply_MooDagMoo(lat, U, v, k), bs[r], tol=1e-14)[0])
         assert st[r]["converged"] and st[r]["true_residual"] <= 1e-10
         assert rel_err(got[r], ref) < 1e-8
     # lighter quarks (larger kappa) need more iterations: the rhs converged at different times
@@ -151,6 +152,7 @@ def test_masked_multi_rhs_cg_8real_links(prec, nrhs, nb, lanes, order):
     x, st = ctx.cg_solve(pack_half(ctx, bs), kappas, prm)
     got = unpack_half(ctx, x, nrhs).reshape(nrhs, lat.Vh, 4, 3)
     for r, k in enumerate(kappas):
-        ref, _, _ = cg(lambda v: dirac.apply_MooDagMoo(lat, U, v, k), bs[r], tol=1e-14)
+        ref = oracle_cached(("moo_cg", dims, "smooth", 5050, 5051 + r, k),
+                            lambda: cg(lambda v: dirac.apply_MooDagMoo(lat, U, v, k), bs[r], tol=1e-14)[0])
         assert st[r]["converged"] and st[r]["true_residual"] <= tol
         assert rel_err(got[r], ref) < (1e-10 if prec == whmc.F64 else 1e-8)

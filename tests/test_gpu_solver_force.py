@@ -14,7 +14,7 @@ from oracle.lattice import Lattice
 from oracle.solve import cg
 from paper_1805_03560_amd import synth, whmc
 
-from gpu_util import algebra_to_numpy, make_ctx, pack_half, rel_err, to_dev, unpack_half
+from gpu_util import algebra_to_numpy, make_ctx, oracle_cached, pack_half, rel_err, to_dev, unpack_half
 
 pytestmark = pytest.mark.gpu
 
@@ -245,5 +245,6 @@ def test_pair_force_kernels_and_chunks(kernel, chunk, dims):
     ctx.set_option(whmc.OPT_FORCE_KERNEL, kernel)
     ctx.set_option(whmc.OPT_FORCE_CHUNK, chunk)
     F = ctx.force(pack_half(ctx, phi), 2, 29, 29, 0.156, 5.6, solver=whmc.cg_params(tol=1e-14, check_every=4))
-    ref = hpe.filtered_force(lat, U, phi, 0.156, 2, 29, tol=1e-14)
+    ref = oracle_cached(("filtered_force", dims, 2140, 2141, 0.156, 2, 29),
+                        lambda: hpe.filtered_force(lat, U, phi, 0.156, 2, 29, tol=1e-14))
     assert rel_err(algebra_to_numpy(ctx, F), ref) < 1e-12

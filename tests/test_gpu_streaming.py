@@ -14,7 +14,7 @@ from oracle.lattice import Lattice
 from oracle.solve import cg
 from paper_1805_03560_amd import synth, whmc
 
-from gpu_util import algebra_to_numpy, make_ctx, pack_full, pack_half, rel_err, unpack_full, unpack_half
+from gpu_util import algebra_to_numpy, make_ctx, oracle_cached, pack_full, pack_half, rel_err, unpack_full, unpack_half
 
 pytestmark = pytest.mark.gpu
 
@@ -94,7 +94,8 @@ def test_streamed_masked_multi_rhs_cg(prec, links, lanes, order):
     x, st = ctx.cg_solve(pack_half(ctx, bs), kappas, prm)
     got = unpack_half(ctx, x, 4)
     for r, k in enumerate(kappas):
-        ref, _, _ = cg(lambda v: dirac.apply_MooDagMoo(lat, U, v, k), bs[r], tol=1e-14)
+        ref = oracle_cached(("moo_cg", DIMS, "smooth", 7020, 7021 + r, k),
+                            lambda: cg(lambda v: dirac.apply_MooDagMoo(lat, U, v, k), bs[r], tol=1e-14)[0])
         assert st[r]["converged"]
         assert rel_err(got[r], ref) < (1e-9 if prec == whmc.F64 else 1e-7), r
 
