@@ -134,10 +134,10 @@ WHMC_DEV Site shift(const Geom& g, const Coords& c, int mu, int d, int nu = 0, i
 WHMC_DEV void load_link(const double2* U18, int Vh, Site s, int mu, SU3<double>& U) {
   LinkF64_18{U18, Vh}.load(s.par, mu, s.cb, U);
 }
-// Link-parallel grids over both parities and the 4 directions: the 8 (parity, mu) workgroups of
-// a block of sites run back to back on one XCD (site_block_grp with 8 groups), so the fields they
-// share (neighbour links, the spinors of every pair) are read from HBM once and then from its L2.
-// Measured at 32^3 x 64: gauge force 2.8 -> 1.3 ms, 24-pair force 17.6 -> 8.1 ms.
+// Link-parallel grid over both parities and the 4 directions (gauge force): the 8 (parity, mu)
+// workgroups of a block of sites run back to back on one XCD (site_block_grp with 8 groups), so the
+// neighbour links they share are read from HBM once and then from its L2.  Measured at 32^3 x 64:
+// 2.8 -> 1.3 ms against parity and mu on grid.z / grid.y.
 WHMC_DEV int link_site(const Geom& g, int& par, int& mu) {
   int grp, slot;
   const int sb = site_block_grp(g, blockIdx.x, gridDim.x, 8, grp, slot);
@@ -312,16 +312,140 @@ __global__ __launch_bounds__(kBlock) void k_pf_force_site(Geom g, const double2*
   force_link<3>(g, par, i, U18, P, npairs, kappa_eff, F, accumulate);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pf_force(Geom g, const double2* __restrict__ U18, PairPtrs P,
-                                                     int npairs, double kappa_eff, double* F, int accumulate) {
-  int par, mu;
-  const int i = link_site(g, par, mu);
-  if (i >= g.Vh) return;
+// Link-parallel form in lockstep.  One workgroup of 512 threads holds the eight (parity, mu) link
+// threads of 64 sites, one wavefront each, and all of them step through the pairs together (a barrier
+// after each pair).  The four directions of a parity then read the same X, Y of a pair at the same
+// time, and the other parity's wavefronts read as their own sites what these read as x / y
+// neighbours, all while the data is in L2.  When the eight workgroups of a site block ran
+// independently, each looping over all pairs, they drifted a pair or two apart, and L2 could not hold
+// a whole pair's data in between.  One such workgroup fills a compute unit (two waves per SIMD), and
+// the blocks of a slice range run side by side on one XCD (site_block_grp, two halves of a 128-site
+// block per workgroup pair), so the z neighbours are fetched by concurrent workgroups too.
+//
+// FP64 spinor of site i in the 64-site block layout, addressed as a uniform base pointer (a pair's
+// field) plus a 32-bit byte offset per lane: a half field is 12 * 16 * Vh bytes, well below 4 GiB for
+// any lattice a context accepts; the 12 components of a site are w = 64 (or Vh % 64 in the last
+// partial block) entries apart.
+WHMC_DEV unsigned spinor_offset(int Vh, int i, unsigned& w16) {
+  const int blk = i >> 6;
+  w16 = (blk < (Vh >> 6) ? 64u : (unsigned)(Vh & 63)) * 16u;
+  return ((unsigned)blk * 64u * 12u + (unsigned)(i & 63)) * 16u;
+}
+WHMC_DEV void load_spinor_at(const double2* base, unsigned off, unsigned w16, Spinor<double>& s) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const double2 v = *(const double2*)((const char*)base + (off + (unsigned)k * w16));
+    s.c[k / 3][k % 3] = {v.x, v.y};
+  }
+}
+
+// Q += sum_s [(1 - g_mu) Yn]_s conj([(1 - g_mu) X]_s), R += sum_s [(1 + g_mu) Y]_s conj([(1 + g_mu) Xn]_s)
+// for one pair: X, Y at the link's site, Xn, Yn at its forward neighbour; one outer product at a time
+template <int MU>
+WHMC_DEV void pair_step(const double2* Xh, const double2* Yh, const double2* Xn, const double2* Yn, unsigned oi,
+                        unsigned wi, unsigned oj, unsigned wj, SU3<double>& Qs, SU3<double>& Rs) {
+  {
+    HalfSpinor<double> h, q;
+    {
+      Spinor<double> s;
+      load_spinor_at(Xh, oi, wi, s);
+      project<MU, -1>(s, q);
+    }
+    {
+      Spinor<double> s;
+      load_spinor_at(Yn, oj, wj, s);
+      project<MU, -1>(s, h);
+    }
+    for (int c = 0; c < 2; ++c)
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) Qs.e[a][b] = Qs.e[a][b] + cjmul(q.c[c][b], h.c[c][a]);
+  }
+  {
+    HalfSpinor<double> h, q;
+    {
+      Spinor<double> s;
+      load_spinor_at(Yh, oi, wi, s);
+      project<MU, +1>(s, h);
+    }
+    {
+      Spinor<double> s;
+      load_spinor_at(Xn, oj, wj, s);
+      project<MU, +1>(s, q);
+    }
+    for (int c = 0; c < 2; ++c)
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) Rs.e[a][b] = Rs.e[a][b] + cjmul(q.c[c][b], h.c[c][a]);
+  }
+}
+
+// F_{x,mu} (+)= -kappa_eff P_TA(s [U Q - R U^dag])
+template <int MU>
+WHMC_DEV void finish_link(const Geom& g, int par, int i, bool wrap, const double2* U18, const SU3<double>& Qs,
+                          const SU3<double>& Rs, double kappa_eff, double* F, int accumulate) {
+  SU3<double> U, A, B;
+  LinkF64_18{U18, g.Vh}.load(par, MU, i, U);
+  matmul(U, Qs, A);
+  matmul_nd(Rs, U, B);
+  const double sgn = (MU == 0 && wrap) ? -1.0 : 1.0;
+  for (int p = 0; p < 3; ++p)
+    for (int q = 0; q < 3; ++q) A.e[p][q] = sgn * (A.e[p][q] - B.e[p][q]);
+  double f[8];
+  ta_coords(A, f);
+  double* out = F + ((size_t)(par * 4 + MU) * 8) * g.Vh + i;
+  for (int k = 0; k < 8; ++k) {
+    const double v = -kappa_eff * f[k];
+    out[(size_t)k * g.Vh] = accumulate ? out[(size_t)k * g.Vh] + v : v;
+  }
+}
+
+constexpr int kForceWG = 512;
+
+__global__ __launch_bounds__(kForceWG) void k_pf_force(Geom g, const double2* __restrict__ U18, PairPtrs P,
+                                                       int npairs, double kappa_eff, double* F, int accumulate) {
+  int half, slot;
+  const int sb = site_block_grp(g, blockIdx.x, gridDim.x, 2, half, slot);
+  const int base = sb * kBlock + half * 64;
+  if (base >= g.Vh) return;   // the whole workgroup: no barrier is left waiting
+  const int par = threadIdx.x >> 8, mu = (threadIdx.x >> 6) & 3;
+  const int i = base + (threadIdx.x & 63);
+  const bool live = i < g.Vh;   // lanes past the last site of a partial block still meet every barrier
+  const int ii = live ? i : base;
+  const Coords c = coords_of(g, ii, par);
+  bool wrap = false;
+  int j;
   switch (mu) {
-    case 0: force_link<0>(g, par, i, U18, P, npairs, kappa_eff, F, accumulate); break;
-    case 1: force_link<1>(g, par, i, U18, P, npairs, kappa_eff, F, accumulate); break;
-    case 2: force_link<2>(g, par, i, U18, P, npairs, kappa_eff, F, accumulate); break;
-    default: force_link<3>(g, par, i, U18, P, npairs, kappa_eff, F, accumulate); break;
+    case 0: j = neighbour<0, +1>(g, c, wrap); break;
+    case 1: j = neighbour<1, +1>(g, c, wrap); break;
+    case 2: j = neighbour<2, +1>(g, c, wrap); break;
+    default: j = neighbour<3, +1>(g, c, wrap); break;
+  }
+  unsigned wi, wj;
+  const unsigned oi = spinor_offset(g.Vh, ii, wi), oj = spinor_offset(g.Vh, j, wj);
+  SU3<double> Qs, Rs;
+  for (int p = 0; p < 3; ++p)
+    for (int q = 0; q < 3; ++q) Qs.e[p][q] = Rs.e[p][q] = {0.0, 0.0};
+#pragma unroll 1
+  for (int k = 0; k < npairs; ++k) {
+    const double2* Xh = par ? P.Xo[k] : P.Xe[k];
+    const double2* Yh = par ? P.Yo[k] : P.Ye[k];
+    const double2* Xn = par ? P.Xe[k] : P.Xo[k];
+    const double2* Yn = par ? P.Ye[k] : P.Yo[k];
+    if (live) {
+      switch (mu) {
+        case 0: pair_step<0>(Xh, Yh, Xn, Yn, oi, wi, oj, wj, Qs, Rs); break;
+        case 1: pair_step<1>(Xh, Yh, Xn, Yn, oi, wi, oj, wj, Qs, Rs); break;
+        case 2: pair_step<2>(Xh, Yh, Xn, Yn, oi, wi, oj, wj, Qs, Rs); break;
+        default: pair_step<3>(Xh, Yh, Xn, Yn, oi, wi, oj, wj, Qs, Rs); break;
+      }
+    }
+    __syncthreads();
+  }
+  if (!live) return;
+  switch (mu) {
+    case 0: finish_link<0>(g, par, i, wrap, U18, Qs, Rs, kappa_eff, F, accumulate); break;
+    case 1: finish_link<1>(g, par, i, wrap, U18, Qs, Rs, kappa_eff, F, accumulate); break;
+    case 2: finish_link<2>(g, par, i, wrap, U18, Qs, Rs, kappa_eff, F, accumulate); break;
+    default: finish_link<3>(g, par, i, wrap, U18, Qs, Rs, kappa_eff, F, accumulate); break;
   }
 }
 
@@ -345,8 +469,8 @@ whmc_status pf_force_pairs(whmc_ctx* c, double* F, const double* const* X_e, con
       hipLaunchKernelGGL(k_pf_force_site, dim3(2 * c->stencil_blocks()), dim3(kBlock), 0, c->stream, c->g, c->U18, P,
                          n, kappa_eff, F, acc);
     else
-      hipLaunchKernelGGL(k_pf_force, dim3(8 * c->stencil_blocks()), dim3(kBlock), 0, c->stream, c->g, c->U18, P, n,
-                         kappa_eff, F, acc);
+      hipLaunchKernelGGL(k_pf_force, dim3(2 * c->stencil_blocks()), dim3(kForceWG), 0, c->stream, c->g, c->U18, P,
+                         n, kappa_eff, F, acc);
     WHMC_HIP(hipGetLastError());
     done += n;
   }
