@@ -102,7 +102,8 @@ whmc_status whmc_set_stream(whmc_ctx* ctx, void* stream);
  *   WHMC_OPT_HOP_CHUNK         chunk of schedule 1, 1 .. blocks per time slice.
  *   WHMC_OPT_FORCE_KERNEL      pseudo-fermion force contraction: 0 = one thread per link, the eight
  *                              (parity, mu) links of 64 sites in one workgroup stepping through the
- *                              pairs together (default), 1 = one thread per site and its four links.
+ *                              pairs together (default; lattices of more than 2^32 / 192 sites per
+ *                              parity use 1), 1 = one thread per site and its four links.
  *   WHMC_OPT_FORCE_CHUNK       (X, Y) pairs summed per launch of that contraction, 1 .. 24 (default
  *                              24); later launches accumulate.  Results agree to rounding.
  *   WHMC_OPT_HOP_WG_PER_CU     occupancy cap of those kernels that work on FP64 spinors with 18- or
