@@ -314,9 +314,9 @@ __global__ __launch_bounds__(kBlock) void k_pf_force_site(Geom g, const double2*
 
 // Link-parallel form in lockstep.  One workgroup of 512 threads holds the eight (parity, mu) link
 // threads of 64 sites, one wavefront each, and all of them step through the pairs together (a barrier
-// after each pair).  The four directions of a parity then read the same X, Y of a pair at the same
-// time, and the other parity's wavefronts read as their own sites what these read as x / y
-// neighbours, all while the data is in L2.  When the eight workgroups of a site block ran
+// per pair).  The four directions of a parity share the local X, Y of a pair through LDS, each loading
+// three of the twelve components, and the other parity's wavefronts read as their own sites what these
+// read as x / y neighbours, all while the data is in L2.  When the eight workgroups of a site block ran
 // independently, each looping over all pairs, they drifted a pair or two apart, and L2 could not hold
 // a whole pair's data in between.  One such workgroup fills a compute unit (two waves per SIMD), and
 // the blocks of a slice range run side by side on one XCD (site_block_grp, two halves of a 128-site
@@ -339,45 +339,6 @@ WHMC_DEV void load_spinor_at(const double2* base, unsigned off, unsigned w16, Sp
   }
 }
 
-// Q += sum_s [(1 - g_mu) Yn]_s conj([(1 - g_mu) X]_s), R += sum_s [(1 + g_mu) Y]_s conj([(1 + g_mu) Xn]_s)
-// for one pair: X, Y at the link's site, Xn, Yn at its forward neighbour; one outer product at a time
-template <int MU>
-WHMC_DEV void pair_step(const double2* Xh, const double2* Yh, const double2* Xn, const double2* Yn, unsigned oi,
-                        unsigned wi, unsigned oj, unsigned wj, SU3<double>& Qs, SU3<double>& Rs) {
-  {
-    HalfSpinor<double> h, q;
-    {
-      Spinor<double> s;
-      load_spinor_at(Xh, oi, wi, s);
-      project<MU, -1>(s, q);
-    }
-    {
-      Spinor<double> s;
-      load_spinor_at(Yn, oj, wj, s);
-      project<MU, -1>(s, h);
-    }
-    for (int c = 0; c < 2; ++c)
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) Qs.e[a][b] = Qs.e[a][b] + cjmul(q.c[c][b], h.c[c][a]);
-  }
-  {
-    HalfSpinor<double> h, q;
-    {
-      Spinor<double> s;
-      load_spinor_at(Yh, oi, wi, s);
-      project<MU, +1>(s, h);
-    }
-    {
-      Spinor<double> s;
-      load_spinor_at(Xn, oj, wj, s);
-      project<MU, +1>(s, q);
-    }
-    for (int c = 0; c < 2; ++c)
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) Rs.e[a][b] = Rs.e[a][b] + cjmul(q.c[c][b], h.c[c][a]);
-  }
-}
-
 // F_{x,mu} (+)= -kappa_eff P_TA(s [U Q - R U^dag])
 template <int MU>
 WHMC_DEV void finish_link(const Geom& g, int par, int i, bool wrap, const double2* U18, const SU3<double>& Qs,
@@ -395,6 +356,45 @@ WHMC_DEV void finish_link(const Geom& g, int par, int i, bool wrap, const double
   for (int k = 0; k < 8; ++k) {
     const double v = -kappa_eff * f[k];
     out[(size_t)k * g.Vh] = accumulate ? out[(size_t)k * g.Vh] + v : v;
+  }
+}
+
+// Q += sum_s [(1 - g_mu) Yn]_s conj([(1 - g_mu) X]_s), R += sum_s [(1 + g_mu) Y]_s conj([(1 + g_mu) Xn]_s)
+// for one pair: X, Y at the link's site (from LDS), Xn, Yn at its forward neighbour (in registers)
+template <int MU>
+WHMC_DEV void pair_step_lds(const double2 (*L)[12][64], int lane, const Spinor<double>& sXn,
+                            const Spinor<double>& sYn, SU3<double>& Qs, SU3<double>& Rs) {
+  {
+    HalfSpinor<double> h, q;
+    {
+      Spinor<double> s;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        const double2 v = L[0][k][lane];
+        s.c[k / 3][k % 3] = {v.x, v.y};
+      }
+      project<MU, -1>(s, q);
+    }
+    project<MU, -1>(sYn, h);
+    for (int c = 0; c < 2; ++c)
+      for (int a = 0; a < 3; ++a)
+        for (int bb = 0; bb < 3; ++bb) Qs.e[a][bb] = Qs.e[a][bb] + cjmul(q.c[c][bb], h.c[c][a]);
+  }
+  {
+    HalfSpinor<double> h, q;
+    {
+      Spinor<double> s;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        const double2 v = L[1][k][lane];
+        s.c[k / 3][k % 3] = {v.x, v.y};
+      }
+      project<MU, +1>(s, h);
+    }
+    project<MU, +1>(sXn, q);
+    for (int c = 0; c < 2; ++c)
+      for (int a = 0; a < 3; ++a)
+        for (int bb = 0; bb < 3; ++bb) Rs.e[a][bb] = Rs.e[a][bb] + cjmul(q.c[c][bb], h.c[c][a]);
   }
 }
 
@@ -424,21 +424,39 @@ __global__ __launch_bounds__(kForceWG) void k_pf_force(Geom g, const double2* __
   SU3<double> Qs, Rs;
   for (int p = 0; p < 3; ++p)
     for (int q = 0; q < 3; ++q) Qs.e[p][q] = Rs.e[p][q] = {0.0, 0.0};
+  // local X, Y of a pair: each of the four direction wavefronts of a parity loads three of the twelve
+  // components of both and writes them to LDS (two buffers, alternating per pair)
+  __shared__ double2 lds[2][2][2][12][64];   // [buffer][parity][X / Y][component][lane]
+  const int lane = threadIdx.x & 63;
 #pragma unroll 1
   for (int k = 0; k < npairs; ++k) {
     const double2* Xh = par ? P.Xo[k] : P.Xe[k];
     const double2* Yh = par ? P.Yo[k] : P.Ye[k];
     const double2* Xn = par ? P.Xe[k] : P.Xo[k];
     const double2* Yn = par ? P.Ye[k] : P.Yo[k];
+    const int b = k & 1;
     if (live) {
-      switch (mu) {
-        case 0: pair_step<0>(Xh, Yh, Xn, Yn, oi, wi, oj, wj, Qs, Rs); break;
-        case 1: pair_step<1>(Xh, Yh, Xn, Yn, oi, wi, oj, wj, Qs, Rs); break;
-        case 2: pair_step<2>(Xh, Yh, Xn, Yn, oi, wi, oj, wj, Qs, Rs); break;
-        default: pair_step<3>(Xh, Yh, Xn, Yn, oi, wi, oj, wj, Qs, Rs); break;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const unsigned kc = (unsigned)(3 * mu + q);
+        lds[b][par][0][3 * mu + q][lane] = *(const double2*)((const char*)Xh + (oi + kc * wi));
+        lds[b][par][1][3 * mu + q][lane] = *(const double2*)((const char*)Yh + (oi + kc * wi));
       }
     }
+    Spinor<double> sXn, sYn;
+    if (live) {
+      load_spinor_at(Xn, oj, wj, sXn);
+      load_spinor_at(Yn, oj, wj, sYn);
+    }
     __syncthreads();
+    if (live) {
+      switch (mu) {
+        case 0: pair_step_lds<0>(lds[b][par], lane, sXn, sYn, Qs, Rs); break;
+        case 1: pair_step_lds<1>(lds[b][par], lane, sXn, sYn, Qs, Rs); break;
+        case 2: pair_step_lds<2>(lds[b][par], lane, sXn, sYn, Qs, Rs); break;
+        default: pair_step_lds<3>(lds[b][par], lane, sXn, sYn, Qs, Rs); break;
+      }
+    }
   }
   if (!live) return;
   switch (mu) {
